@@ -297,7 +297,7 @@ class Planner:
         out = np.zeros(16)
         self.lib.orc_planner_info(self.h, out)
         keys = ["U", "C", "inc_f", "inc_b", "first_iter", "L", "H", "k_lo", "k_hi", "iter", "overflow",
-                "n_active", "total", "n_pools"]
+                "n_active", "total", "n_pools", "edge_checks", "bridge_checks"]
         return {k: out[i] for i, k in enumerate(keys)}
 
     def counts(self):

@@ -241,7 +241,8 @@ int orc_edge_check(const orc_scene *sc, const double *xa_in, const double *xb_in
     double x[ORC_MAX_DOF + 1];
     for (int64_t j = 0; j <= n; ++j) {
         double s = (double)j / (double)n;
-        for (int c = 0; c <= d; ++c) x[c] = xa[c] + s * (xb[c] - xa[c]);
+        /* s = 1 is the endpoint itself */
+        for (int c = 0; c <= d; ++c) x[c] = j == n ? xb[c] : xa[c] + s * (xb[c] - xa[c]);
         double m;
         int ok = orc_state_valid(sc, x, &m);
         mabs = fmin(mabs, fabs(m));
@@ -497,6 +498,7 @@ struct orc_planner {
     int32_t active_list[256];
     int64_t iter;
     int32_t overflow;
+    int64_t n_edge_checks, n_bridge_checks; /* edges decided (for throughput) */
 };
 
 static int64_t push_node(orc_planner *p, int pool, const double *x, int32_t parent, double cost, double rootT) {
@@ -879,6 +881,7 @@ int orc_planner_extend(orc_planner *p, int64_t B, const int8_t *dir, const uint8
         int32_t fh;
         double em;
         int ok = orc_edge_check(sc, k->xn, k->xnew, &fh, NULL, &em, NULL);
+        p->n_edge_checks++;
         if (edge_margin) edge_margin[i] = em;
         if (!ok) { k->status = ORC_ST_TRAPPED; continue; }
         k->status = ORC_ST_ADVANCED;
@@ -903,6 +906,7 @@ int orc_planner_extend(orc_planner *p, int64_t B, const int8_t *dir, const uint8
         if (b >= 0) {
             double bm;
             int bok = orc_edge_check(sc, k->xnew, p->x + b * w, NULL, NULL, &bm, NULL);
+            p->n_bridge_checks++;
             if (bridge_margin) bridge_margin[i] = bm;
             k->bridge_ok = (uint8_t)bok;
             if (bok) {
@@ -1049,6 +1053,8 @@ void orc_planner_info(const orc_planner *p, double *out /* 16 */) {
     out[11] = (double)p->n_active;
     out[12] = (double)p->total;
     out[13] = (double)p->n_pools;
+    out[14] = (double)p->n_edge_checks;
+    out[15] = (double)p->n_bridge_checks;
 }
 
 void orc_planner_counts(const orc_planner *p, int64_t *counts) {

@@ -1,0 +1,1388 @@
+// extend.hip -- the batched space-time extend step (Alg. 1) driven by the
+// interval-root (Alg. 2) or root-recycling (Alg. 3) allocation.
+//
+// One batch is a fixed sequence of kernels on one stream:
+//   sample   a1  Philox draws -> direction, group/slot, root time T, root check,
+//                q_r, t_r (Eq. 6), p_new rule
+//   prep         snapshot of pool counts and U; workers bucketed by node set
+//   scan     a2  nearest node: tiles of 64 queries (one per lane) stream a
+//                node set from HBM through LDS; packed (distance, index) keys
+//                are merged with 64-bit atomicMin, so ties go to the lowest index
+//   steer    a3  alpha = min(1, eta/rho) (interval root) or Eq. 8 (recycling)
+//   check    a4  edge checks (collide.hip), any-hit early exit
+//   insert   a5  one block per pool: prefix sum over workers in order, slots
+//                after the snapshot count, virtual roots materialised first
+//   bridge   a6  best-ranked candidate in the opposite set (arrival, rho, index),
+//                per-chunk partials merged per worker, then its edge check
+//   publish  a7  lexicographic minimum of (U', C', worker) against (U, C)
+//   roots    a8/a9 allocation update after a strict drop of U
+// Every worker sees the trees as they were when the batch started.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#include "rng.hpp"
+#include "st_internal.hpp"
+
+namespace st {
+
+constexpr int kScanThreads = 64;
+constexpr int kMaxNch = 64;
+constexpr unsigned long long kNoKey = ~0ull;
+constexpr int kSetAllBackward = -2;
+
+__device__ __forceinline__ unsigned long long pack_key(float dist_key, int32_t idx) {
+    return ((unsigned long long)__float_as_uint(dist_key) << 32) | (uint32_t)idx;
+}
+
+__device__ __forceinline__ int worker_pool(int8_t dir, int32_t grp) { return dir == 0 ? 0 : 1 + grp; }
+
+// ---------------------------------------------------------------------------
+// a1: sampling
+// ---------------------------------------------------------------------------
+
+struct SampleArgs {
+    SceneDev sc;
+    WindowsDev win;
+    const PlanDev *pl;
+    int32_t variant, N;
+    float p_guided, p_new;
+    uint32_t seed, pid;
+    int64_t iter, B;
+    st_samples out;
+};
+
+// Root time for group g of the current interval-root allocation, in double:
+// with probability p_guided (when the guided windows below Ubar are not empty)
+// a portion of the group's guided share chosen in proportion to its length and
+// a uniform time inside it; otherwise uniform on I_g.
+__device__ double ir_root_time(const WindowsDev &w, const PlanDev *pl, int g, const uint32_t *u, float p_guided) {
+    const double L = w.L, Ubar = pl->Ubar, G = pl->G;
+    const int N = w.N;
+    if (unit24f(u[1]) < p_guided && G > 0.0 && pl->jstar > 0) {
+        const double c_lo = G * g / N, c_hi = G * (g + 1) / N;
+        const double c = c_lo + unit24d(u[2]) * (c_hi - c_lo);
+        // window j with cum[j] <= c < cum[j] + len_j
+        int lo = 0, hi = pl->jstar - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (w.cum[mid] <= c) lo = mid;
+            else hi = mid - 1;
+        }
+        const int j = lo;
+        const double len = fmin(w.hi[j], Ubar) - w.lo[j];
+        const double a = fmax(c_lo, w.cum[j]), b = fmin(c_hi, w.cum[j] + len);
+        return w.lo[j] + (a - w.cum[j]) + unit24d(u[3]) * (b - a);
+    }
+    const double width = (Ubar - L) / N;
+    const double I0 = L + g * width, I1 = L + (g + 1) * width;
+    return I0 + unit24d(u[3]) * (I1 - I0);
+}
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+    extern __shared__ float4 lds[];
+    const SceneDev &sc = a.sc;
+    const bool ir = a.variant == ST_INTERVAL_ROOT;
+    if (ir) stage_obstacles(sc, lds);
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = w < a.B;
+    const PlanDev *pl = a.pl;
+    uint32_t u[16];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const U4 r = philox4x32_10((uint32_t)a.iter, (uint32_t)w, (uint32_t)b, 0u, a.seed, a.pid);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) u[4 * b + k] = r.x[k];
+    }
+    const int8_t dir = (int8_t)((w + a.iter) & 1);
+    uint8_t flags = 0;
+    int32_t g = 0;
+    float T = 0.f, tr = 0.f;
+    float q[kMaxDof];
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j)
+        q[j] = j < sc.d ? sc.q_lo[j] + unit24f(u[4 + j]) * (sc.q_hi[j] - sc.q_lo[j]) : 0.f;
+    bool check_root = false;
+    if (ir) {
+        g = index24(u[0], a.N);
+        if (!act || pl->done) {
+            flags |= ST_FLAG_SKIP;
+        } else {
+            T = (float)ir_root_time(a.win, pl, g, u, a.p_guided);
+            check_root = true;
+        }
+    } else if (act && dir == 1) {
+        const int64_t k = w >> 1;
+        const int na = pl->n_active;
+        if (na == 0) {
+            flags |= ST_FLAG_SKIP;
+        } else {
+            g = pl->active_list[k % na];
+            T = pl->slotT[g];
+        }
+    }
+    if (ir) {
+        // the proposed root (q_g, T) is checked at its own time
+        const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, sc.q_g, T, check_root, 1ull << lane, 0ull);
+        if (check_root) {
+            if (hit) flags |= ST_FLAG_SKIP;
+            // Eq. 6: t_r ~ U[D(q_s, q_r)/v, T - D(q_r, q_g)/v], empty interval rejected
+            float ds = 0.f, dg = 0.f;
+#pragma unroll
+            for (int j = 0; j < kMaxDof; ++j) {
+                if (j < sc.d) {
+                    const float e1 = q[j] - sc.q_s[j], e2 = sc.q_g[j] - q[j];
+                    ds = fmaf(e1, e1, ds);
+                    dg = fmaf(e2, e2, dg);
+                }
+            }
+            const float lo = sqrtf(ds) / sc.v, hi = T - sqrtf(dg) / sc.v;
+            if (hi < lo) flags |= ST_FLAG_SKIP;
+            else tr = lo + unit24f(u[11]) * (hi - lo);
+            if (dir == 1 && (!(pl->minRootT[g] < pl->U) || unit24f(u[12]) <= a.p_new)) flags |= ST_FLAG_USE_NEW;
+        }
+    }
+    if (!act) return;
+    a.out.dir[w] = dir;
+    a.out.flags[w] = flags;
+    a.out.grp[w] = g;
+    a.out.T[w] = T;
+    for (int j = 0; j < sc.d; ++j) a.out.qr[(int64_t)j * a.B + w] = q[j];
+    a.out.tr[w] = tr;
+}
+
+// ---------------------------------------------------------------------------
+// bucketing of queries by node set
+// ---------------------------------------------------------------------------
+
+struct PrepArgs {
+    PlanDev *pl;
+    int32_t variant, n_pools, d;
+    int64_t B;
+    st_samples s;       // mode 0 (nearest node)
+    const int8_t *status; // mode 1 (bridges)
+    const int8_t *dir;
+    int32_t *set_of, *order;
+    int4 *tiles;
+    int32_t *n_tiles;
+    float *qbuf;        // mode 0: AoS copy of the queries
+    unsigned long long *keys;
+    int32_t mode;       // 0 nearest node, 1 bridges
+};
+
+__global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
+    __shared__ int cnt[kMaxPools + 2], cur[kMaxPools + 2];
+    const int tid = threadIdx.x;
+    const int nsets = a.mode == 0 ? a.n_pools : 2;
+    for (int i = tid; i < nsets; i += blockDim.x) cnt[i] = 0;
+    if (a.mode == 0 && tid == 0) {
+        // the snapshot every worker of this batch sees
+        for (int i = 0; i < a.n_pools; ++i) a.pl->count_snap[i] = a.pl->count[i];
+        a.pl->U_snap = a.pl->U;
+        a.pl->improved = 0;
+    }
+    __syncthreads();
+    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+        int set = -1;
+        if (a.mode == 0) {
+            const uint8_t f = a.s.flags[w];
+            const int8_t dir = a.s.dir[w];
+            const int32_t g = a.s.grp[w];
+            if (!(f & ST_FLAG_SKIP)) {
+                if (dir == 0) set = 0;
+                else if (g >= 0 && g < a.n_pools - 1 &&
+                         !(a.variant == ST_INTERVAL_ROOT && (f & ST_FLAG_USE_NEW)))
+                    set = 1 + g;
+            }
+            for (int j = 0; j < a.d; ++j) a.qbuf[w * (a.d + 1) + j] = a.s.qr[(int64_t)j * a.B + w];
+            a.qbuf[w * (a.d + 1) + a.d] = a.s.tr[w];
+            a.keys[w] = kNoKey;
+        } else {
+            // forward new nodes bridge into the backward forest (set 0), backward
+            // new nodes into the forward tree (set 1)
+            if (a.status[w] == ST_STATUS_ADVANCED) set = a.dir[w] == 0 ? 0 : 1;
+        }
+        a.set_of[w] = set;
+        if (set >= 0) atomicAdd(&cnt[set], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int off = 0, t = 0;
+        for (int s = 0; s < nsets; ++s) {
+            cur[s] = off;
+            for (int k = 0; k < cnt[s]; k += kScanThreads) {
+                int set_id, sigma;
+                if (a.mode == 0) {
+                    set_id = s;
+                    sigma = s == 0 ? 1 : -1;
+                } else {
+                    // a bridge from x_new in direction sigma needs sigma (t_y - t_new) > 0,
+                    // i.e. the nearest-node rule with the opposite sign
+                    set_id = s == 0 ? kSetAllBackward : 0;
+                    sigma = s == 0 ? -1 : 1;
+                }
+                a.tiles[t++] = make_int4(set_id, off + k, min(kScanThreads, cnt[s] - k), sigma);
+            }
+            off += cnt[s];
+        }
+        a.n_tiles[0] = t;
+    }
+    __syncthreads();
+    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+        const int set = a.set_of[w];
+        if (set >= 0) a.order[atomicAdd(&cur[set], 1)] = (int32_t)w;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a2 / a6: node-set scans
+// ---------------------------------------------------------------------------
+
+enum { kScanRho = 0, kScanConfig = 1, kScanBridge = 2 };
+
+struct ScanArgs {
+    TreeDev tree;
+    const PlanDev *pl;
+    int32_t use_snap, variant;
+    float v;
+    const float *qbuf;      // AoS queries [.][d+1]
+    const int32_t *order;   // query ids per tile slot (null: identity)
+    const int4 *tiles;
+    const int32_t *n_tiles;
+    unsigned long long *keys;  // nearest node: per-query atomic minimum
+    unsigned long long *pkey;  // bridges: [nch][pstride]
+    int32_t *pidx;
+    int64_t pstride;
+    int32_t nch;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
+    __shared__ float sx[kScanThreads][8];
+    __shared__ float sT[kScanThreads];
+    const int t = blockIdx.x;
+    if (t >= a.n_tiles[0]) return;
+    const int lane = threadIdx.x;
+    const int4 tile = a.tiles[t];
+    const int set = tile.x, n = tile.z;
+    const float sv = (float)tile.w * a.v;  // sigma * v
+    const int d = a.tree.d;
+    const bool act = lane < n;
+    const int q = act ? (a.order ? a.order[tile.y + lane] : tile.y + lane) : 0;
+    float qx[kMaxDof];
+    float aq = 0.f;
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j) qx[j] = (act && j < d) ? a.qbuf[(int64_t)q * (d + 1) + j] : 0.f;
+    if (act) aq = sv * a.qbuf[(int64_t)q * (d + 1) + d];
+    const PlanDev *pl = a.pl;
+    const float U = a.use_snap ? pl->U_snap : pl->U;
+    const int y = blockIdx.y;
+    float best = INFINITY, bestT = INFINITY;
+    int32_t bi = -1;
+    const int p_lo = set >= 0 ? set : 1, p_hi = set >= 0 ? set + 1 : a.tree.n_pools;
+    const float *X = a.tree.x;
+    const int64_t total = a.tree.total;
+    for (int p = p_lo; p < p_hi; ++p) {
+        if (a.variant == ST_ROOT_RECYCLING && set < 0 && !pl->slot_active[p - 1]) continue;
+        const int64_t cnt = a.use_snap ? pl->count_snap[p] : pl->count[p];
+        const int64_t c0 = (int64_t)y * cnt / a.nch, c1 = (int64_t)(y + 1) * cnt / a.nch;
+        const int64_t base = pool_base(a.tree, p);
+        const bool filt = a.variant == ST_INTERVAL_ROOT && p > 0;
+        for (int64_t c = c0; c < c1; c += kScanThreads) {
+            const int64_t i = c + lane;
+            const bool ok = i < c1;
+            const int64_t gi = base + i;
+#pragma unroll
+            for (int j = 0; j < kMaxDof; ++j)
+                if (j < d) sx[lane][j] = ok ? X[(int64_t)j * total + gi] : 0.f;
+            float tn = ok ? X[(int64_t)d * total + gi] : 0.f;
+            float rt = (ok && (filt || MODE == kScanBridge)) ? a.tree.rootT[gi] : 0.f;
+            // inactive backward trees (root at or after U) are hidden behind a NaN time
+            if (!ok || (filt && !(rt < U))) tn = __int_as_float(0x7fc00000);
+            sx[lane][7] = sv * tn;
+            sT[lane] = rt;
+            __syncthreads();
+            const int m = (int)min<int64_t>(kScanThreads, c1 - c);
+            if (act) {
+                for (int k = 0; k < m; ++k) {
+                    float D2 = 0.f;
+#pragma unroll
+                    for (int j = 0; j < kMaxDof; ++j) {
+                        if (j < d) {
+                            const float e = sx[k][j] - qx[j];
+                            D2 = fmaf(e, e, D2);
+                        }
+                    }
+                    if (MODE == kScanConfig) {
+                        if (D2 < best) { best = D2; bi = (int32_t)(base + c + k); }
+                    } else {
+                        // Eq. 7: admissible iff sigma (t_q - t) > 0 and D <= v sigma (t_q - t)
+                        const float vd = aq - sx[k][7];
+                        const float w2 = vd * fabsf(vd);
+                        const bool adm = (D2 <= w2) && (w2 > 0.f);
+                        const float key = D2 + w2;
+                        if (MODE == kScanRho) {
+                            if (adm && key < best) { best = key; bi = (int32_t)(base + c + k); }
+                        } else {
+                            const float arr = set < 0 ? sT[k] : 0.f;
+                            if (adm && (arr < bestT || (arr == bestT && key < best))) {
+                                bestT = arr;
+                                best = key;
+                                bi = (int32_t)(base + c + k);
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (!act) return;
+    if (MODE == kScanBridge) {
+        a.pkey[(int64_t)y * a.pstride + q] = bi < 0 ? kNoKey : (((unsigned long long)__float_as_uint(bestT) << 32) |
+                                                                 __float_as_uint(best));
+        a.pidx[(int64_t)y * a.pstride + q] = bi;
+    } else if (bi >= 0) {
+        atomicMin(&a.keys[q], pack_key(best, bi));
+    }
+}
+
+// ---------------------------------------------------------------------------
+// a3: steering
+// ---------------------------------------------------------------------------
+
+struct SteerArgs {
+    SceneDev sc;
+    TreeDev tree;
+    const PlanDev *pl;
+    int32_t variant;
+    float eta;
+    int64_t B;
+    st_samples s;
+    Work w;
+};
+
+__global__ __launch_bounds__(256) void k_steer(SteerArgs a) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.B) return;
+    const SceneDev &sc = a.sc;
+    const int d = sc.d, W = d + 1;
+    Work &k = a.w;
+    k.new_idx[w] = -1;
+    k.parent[w] = -1;
+    k.edge_valid[w] = 0;
+    const uint8_t f = a.s.flags[w];
+    const int8_t dir = a.s.dir[w];
+    const int32_t g = a.s.grp[w];
+    // a backward worker must name an existing group / slot
+    if ((f & ST_FLAG_SKIP) || (dir != 0 && (g < 0 || g >= a.tree.n_pools - 1))) {
+        k.status[w] = ST_STATUS_SKIPPED;
+        return;
+    }
+    k.status[w] = ST_STATUS_TRAPPED;
+    const float sigma = dir == 0 ? 1.f : -1.f;
+    float xr[kMaxDof + 1], xn[kMaxDof + 1], xnew[kMaxDof + 1];
+    for (int j = 0; j < d; ++j) xr[j] = a.s.qr[(int64_t)j * a.B + w];
+    xr[d] = a.s.tr[w];
+    const bool virt = a.variant == ST_INTERVAL_ROOT && dir == 1 && (f & ST_FLAG_USE_NEW);
+    int32_t idx = -1;
+    if (virt) {
+        for (int j = 0; j < d; ++j) xn[j] = sc.q_g[j];
+        xn[d] = a.s.T[w];
+    } else {
+        const unsigned long long key = k.nn_key[w];
+        if (key == kNoKey) return;  // TRAPPED: nothing admissible
+        idx = (int32_t)(key & 0xffffffffu);
+        for (int j = 0; j <= d; ++j) xn[j] = a.tree.x[(int64_t)j * a.tree.total + idx];
+    }
+    float D2 = 0.f;
+    for (int j = 0; j < d; ++j) {
+        const float e = xr[j] - xn[j];
+        D2 = fmaf(e, e, D2);
+    }
+    float step;
+    if (a.variant == ST_INTERVAL_ROOT) {
+        const float vd = sigma * sc.v * (xr[d] - xn[d]);
+        const float w2 = vd * fabsf(vd);
+        if (!(D2 <= w2 && w2 > 0.f)) return;  // rho infinite
+        const float rho = sqrtf(0.5f * (D2 + w2));
+        const float alpha = fminf(1.f, a.eta / rho);  // Alg. 1: same fraction in q and t
+        for (int j = 0; j <= d; ++j) xnew[j] = fmaf(alpha, xr[j] - xn[j], xn[j]);
+        float s2 = 0.f;
+        for (int j = 0; j < d; ++j) {
+            const float e = xnew[j] - xn[j];
+            s2 = fmaf(e, e, s2);
+        }
+        step = sqrtf(s2);
+    } else {
+        const float D = sqrtf(D2);
+        if (!(D > 0.f)) return;  // no proposal
+        const float fr = fminf(1.f, a.eta / D);
+        float s2 = 0.f;
+        for (int j = 0; j < d; ++j) {
+            xnew[j] = fmaf(fr, xr[j] - xn[j], xn[j]);
+            const float e = xnew[j] - xn[j];
+            s2 = fmaf(e, e, s2);
+        }
+        step = sqrtf(s2);
+        xnew[d] = xn[d] + sigma * step / sc.v;  // Eq. 8: maximum-speed timing
+    }
+    if (!(xnew[d] >= 0.f && xnew[d] <= sc.H)) return;  // leaves [0, H]
+    for (int j = 0; j <= d; ++j) {
+        k.xn[w * W + j] = xn[j];
+        k.xnew[w * W + j] = xnew[j];
+    }
+    k.edge_valid[w] = 1;
+    k.parent[w] = idx;
+    k.cost_new[w] = (virt ? 0.f : a.tree.cost[idx]) + step;
+    k.rootT_new[w] = dir == 0 ? 0.f : (virt ? a.s.T[w] : a.tree.rootT[idx]);
+}
+
+// ---------------------------------------------------------------------------
+// a5: insertion, one block per pool, workers in index order
+// ---------------------------------------------------------------------------
+
+struct InsertArgs {
+    SceneDev sc;
+    TreeDev tree;
+    PlanDev *pl;
+    int32_t variant;
+    int64_t B;
+    st_samples s;
+    Work w;
+};
+
+__global__ __launch_bounds__(1024) void k_insert(InsertArgs a) {
+    __shared__ int wsum[32];
+    __shared__ int s_total, s_last;
+    const int p = blockIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int nw = blockDim.x >> 6;
+    PlanDev *pl = a.pl;
+    Work &k = a.w;
+    const int d = a.tree.d, W = d + 1;
+    const int64_t base = pool_base(a.tree, p);
+    const int64_t snap = pl->count_snap[p];
+    const int64_t avail = pool_cap(a.tree, p) - snap;
+    int64_t running = 0;
+    if (tid == 0) s_last = 0;
+    for (int64_t c0 = 0; c0 < a.B; c0 += blockDim.x) {
+        const int64_t w = c0 + tid;
+        int need = 0;
+        bool virt = false;
+        if (w < a.B && k.edge_valid[w] && worker_pool(a.s.dir[w], a.s.grp[w]) == p) {
+            if (!k.edge_free[w]) {
+                k.status[w] = ST_STATUS_TRAPPED;  // the extension collides
+            } else {
+                virt = k.parent[w] < 0;
+                need = virt ? 2 : 1;
+            }
+        }
+        // block-wide exclusive prefix of `need`
+        int incl = need;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        if (tid == 0) {
+            int acc = 0;
+            for (int i = 0; i < nw; ++i) {
+                const int v = wsum[i];
+                wsum[i] = acc;
+                acc += v;
+            }
+            s_total = acc;
+        }
+        __syncthreads();
+        const int64_t off = running + wsum[wv] + incl - need;
+        if (need > 0) {
+            if (off + need > avail) {
+                k.status[w] = ST_STATUS_DROPPED;
+                pl->overflow = 1;
+            } else {
+                int64_t idx = base + snap + off;
+                int32_t par = k.parent[w];
+                if (virt) {
+                    // materialise the backward tree rooted at (q_g, T)
+                    const float T = a.s.T[w];
+                    for (int j = 0; j < d; ++j) a.tree.x[(int64_t)j * a.tree.total + idx] = a.sc.q_g[j];
+                    a.tree.x[(int64_t)d * a.tree.total + idx] = T;
+                    a.tree.parent[idx] = -1;
+                    a.tree.cost[idx] = 0.f;
+                    a.tree.rootT[idx] = T;
+                    atomicMin((int *)&pl->minRootT[p - 1], __float_as_int(T));
+                    par = (int32_t)idx;
+                    k.parent[w] = par;
+                    ++idx;
+                }
+                for (int j = 0; j <= d; ++j) a.tree.x[(int64_t)j * a.tree.total + idx] = k.xnew[w * W + j];
+                a.tree.parent[idx] = par;
+                a.tree.cost[idx] = k.cost_new[w];
+                a.tree.rootT[idx] = k.rootT_new[w];
+                k.new_idx[w] = (int32_t)idx;
+                k.status[w] = ST_STATUS_ADVANCED;
+                atomicMax(&s_last, (int)(off + need));
+            }
+        }
+        running += s_total;
+        __syncthreads();
+    }
+    if (tid == 0) pl->count[p] = (int32_t)(snap + s_last);
+}
+
+// ---------------------------------------------------------------------------
+// a6: bridge selection merge
+// ---------------------------------------------------------------------------
+
+struct BridgeArgs {
+    TreeDev tree;
+    int64_t B;
+    int32_t nch;
+    const int8_t *dir;
+    Work w;
+};
+
+__global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.B) return;
+    Work &k = a.w;
+    const int d = a.tree.d, W = d + 1;
+    k.bridge[w] = -1;
+    k.br_valid[w] = 0;
+    k.Up[w] = INFINITY;
+    k.Cp[w] = INFINITY;
+    if (k.status[w] != ST_STATUS_ADVANCED) return;
+    unsigned long long bk = kNoKey;
+    int32_t bi = -1;
+    for (int y = 0; y < a.nch; ++y) {
+        const unsigned long long kk = k.br_key[(int64_t)y * a.B + w];
+        const int32_t ii = k.br_idx[(int64_t)y * a.B + w];
+        if (ii >= 0 && (kk < bk || (kk == bk && (uint32_t)ii < (uint32_t)bi))) {
+            bk = kk;
+            bi = ii;
+        }
+    }
+    if (bi < 0) return;
+    float D2 = 0.f;
+    for (int j = 0; j <= d; ++j) {
+        const float v = a.tree.x[(int64_t)j * a.tree.total + bi];
+        k.xb[w * W + j] = v;
+        if (j < d) {
+            const float e = v - k.xnew[w * W + j];
+            D2 = fmaf(e, e, D2);
+        }
+    }
+    k.bridge[w] = bi;
+    k.br_valid[w] = 1;
+    k.Up[w] = a.dir[w] == 0 ? a.tree.rootT[bi] : k.rootT_new[w];
+    k.Cp[w] = k.cost_new[w] + sqrtf(D2) + a.tree.cost[bi];
+}
+
+// ---------------------------------------------------------------------------
+// a7: incumbent publish (lexicographic (U', C', worker) minimum)
+// ---------------------------------------------------------------------------
+
+struct PublishArgs {
+    PlanDev *pl;
+    int64_t B;
+    const int8_t *dir;
+    Work w;
+    st_extend_out out;
+};
+
+__device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, float c2, int w2) {
+    if (u1 != u2) return u1 < u2;
+    if (c1 != c2) return c1 < c2;
+    return (uint32_t)w1 < (uint32_t)w2;
+}
+
+__global__ __launch_bounds__(1024) void k_publish(PublishArgs a) {
+    __shared__ float sU[1024], sC[1024];
+    __shared__ int sW[1024];
+    const int tid = threadIdx.x;
+    Work &k = a.w;
+    float bu = INFINITY, bc = INFINITY;
+    int bw = -1;
+    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+        const bool ok = k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w] && k.br_free[w];
+        if (!ok) {
+            k.Up[w] = INFINITY;
+            k.Cp[w] = INFINITY;
+        } else if (lex_less(k.Up[w], k.Cp[w], (int)w, bu, bc, bw)) {
+            bu = k.Up[w];
+            bc = k.Cp[w];
+            bw = (int)w;
+        }
+    }
+    sU[tid] = bu;
+    sC[tid] = bc;
+    sW[tid] = bw;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (tid < s && lex_less(sU[tid + s], sC[tid + s], sW[tid + s], sU[tid], sC[tid], sW[tid])) {
+            sU[tid] = sU[tid + s];
+            sC[tid] = sC[tid + s];
+            sW[tid] = sW[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        PlanDev *pl = a.pl;
+        const int w = sW[0];
+        if (w >= 0 && (sU[0] < pl->U || (sU[0] == pl->U && sC[0] < pl->C))) {
+            pl->improved = sU[0] < pl->U ? 2 : 1;
+            pl->U = sU[0];
+            pl->C = sC[0];
+            if (a.dir[w] == 0) {
+                pl->inc_f = k.new_idx[w];
+                pl->inc_b = k.bridge[w];
+            } else {
+                pl->inc_f = k.bridge[w];
+                pl->inc_b = k.new_idx[w];
+            }
+            if (pl->first_iter < 0) pl->first_iter = pl->iter;
+        }
+        pl->iter += 1;
+    }
+    // optional caller outputs
+    const st_extend_out &o = a.out;
+    const int W = 0;
+    (void)W;
+    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+        if (o.status) o.status[w] = k.status[w];
+        if (o.parent) o.parent[w] = k.parent[w];
+        if (o.new_idx) o.new_idx[w] = k.new_idx[w];
+        if (o.bridge) o.bridge[w] = k.bridge[w];
+        if (o.bridge_ok) o.bridge_ok[w] = (k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w]) ? k.br_free[w] : 0;
+        if (o.Up) o.Up[w] = k.Up[w];
+        if (o.Cp) o.Cp[w] = k.Cp[w];
+    }
+}
+
+struct XnewOutArgs {
+    int64_t B;
+    int32_t d;
+    const int8_t *status;
+    const float *xnew;
+    float *out;
+};
+
+__global__ void k_xnew_out(XnewOutArgs a) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.B) return;
+    const bool adv = a.status[w] >= ST_STATUS_ADVANCED;
+    for (int j = 0; j <= a.d; ++j) a.out[(int64_t)j * a.B + w] = adv ? a.xnew[w * (a.d + 1) + j] : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// a8 / a9: allocation update after a strict drop of U
+// ---------------------------------------------------------------------------
+
+struct RootsArgs {
+    SceneDev sc;
+    TreeDev tree;
+    WindowsDev win;
+    PlanDev *pl;
+    int32_t variant, N;
+};
+
+__global__ __launch_bounds__(256) void k_roots(RootsArgs a) {
+    __shared__ int cand[kMaxGroups], assign[kMaxGroups], donor[kMaxGroups];
+    __shared__ int s_kend;
+    PlanDev *pl = a.pl;
+    if (pl->improved != 2) return;
+    const int tid = threadIdx.x, N = a.N;
+    const WindowsDev &w = a.win;
+    if (a.variant == ST_INTERVAL_ROOT) {
+        // repartition below Ubar = min(H, U); trees rooted at T >= U drop out
+        // of the scans through their root time
+        if (tid == 0) {
+            const double Ubar = fmin(w.H, (double)pl->U);
+            int j = 0;
+            int lo = 0, hi = w.nw;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (w.lo[mid] < Ubar) lo = mid + 1;
+                else hi = mid;
+            }
+            j = lo;
+            pl->Ubar = Ubar;
+            pl->jstar = j;
+            pl->G = j > 0 ? w.cum[j - 1] + (fmin(w.hi[j - 1], Ubar) - w.lo[j - 1]) : 0.0;
+            pl->done = !(w.L < Ubar);
+        }
+        return;
+    }
+    const float U = pl->U;
+    if (tid < N) {
+        const float T = pl->slotT[tid];
+        if (T >= U) pl->slot_active[tid] = 0;
+        donor[tid] = T > U ? 1 : 0;
+        assign[tid] = -1;
+    }
+    if (tid == 0) {
+        // first grid index whose time (as stored) is not below U
+        int k = w.k_lo;
+        while (k <= w.k_hi && (float)((double)k * w.dt) < U) ++k;
+        s_kend = k;
+    }
+    __syncthreads();
+    const int64_t K = s_kend - w.k_lo;
+    if (tid < N && K > 0) {
+        const int64_t a0 = w.k_lo + (K * tid) / N, b0 = w.k_lo + (K * (tid + 1)) / N;
+        bool occupied = false;
+        for (int s = 0; s < N; ++s)
+            if (pl->slot_active[s] && pl->slotK[s] >= a0 && pl->slotK[s] < b0) occupied = true;
+        int c = -1;
+        if (!occupied)
+            for (int64_t k = a0; k < b0; ++k)
+                if (w.gfree[k - w.k_lo]) {
+                    c = (int)k;
+                    break;
+                }
+        cand[tid] = c;
+    } else if (tid < N) {
+        cand[tid] = -1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int s = 0;
+        for (int st_ = 0; st_ < N; ++st_) {
+            if (cand[st_] < 0) continue;
+            while (s < N && !donor[s]) ++s;
+            if (s >= N) break;
+            assign[s++] = cand[st_];
+        }
+    }
+    __syncthreads();
+    if (tid < N && assign[tid] >= 0) {
+        const int s = tid;
+        const int k = assign[s];
+        const float T = (float)((double)k * w.dt);
+        const int64_t idx = pool_base(a.tree, 1 + s);
+        for (int j = 0; j < a.sc.d; ++j) a.tree.x[(int64_t)j * a.tree.total + idx] = a.sc.q_g[j];
+        a.tree.x[(int64_t)a.sc.d * a.tree.total + idx] = T;
+        a.tree.parent[idx] = -1;
+        a.tree.cost[idx] = 0.f;
+        a.tree.rootT[idx] = T;
+        pl->count[1 + s] = 1;
+        pl->slot_gen[s] += 1;
+        pl->slotT[s] = T;
+        pl->slotK[s] = k;
+        pl->slot_active[s] = 1;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int na = 0;
+        for (int s = 0; s < N; ++s)
+            if (pl->slot_active[s]) pl->active_list[na++] = s;
+        pl->n_active = na;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// nearest-node results for the C ABI
+// ---------------------------------------------------------------------------
+
+__global__ void k_nn_out(int64_t M, int metric, const unsigned long long *keys, int32_t *idx, float *dist) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    const unsigned long long k = keys[i];
+    const bool none = k == kNoKey;
+    idx[i] = none ? -1 : (int32_t)(k & 0xffffffffu);
+    if (dist) {
+        const float kf = __uint_as_float((uint32_t)(k >> 32));
+        dist[i] = none ? INFINITY : (metric == ST_METRIC_RHO ? sqrtf(0.5f * kf) : sqrtf(kf));
+    }
+}
+
+__global__ void k_fill_tiles(int64_t M, int set, int sigma, int4 *tiles, int32_t *n_tiles, unsigned long long *keys) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nt = (M + kScanThreads - 1) / kScanThreads;
+    if (i < nt) tiles[i] = make_int4(set, (int)(i * kScanThreads), (int)min<int64_t>(kScanThreads, M - i * kScanThreads), sigma);
+    if (i == 0) n_tiles[0] = (int32_t)nt;
+    for (int64_t j = i; j < M; j += (int64_t)gridDim.x * blockDim.x) keys[j] = kNoKey;
+}
+
+// ---------------------------------------------------------------------------
+// path extraction and timestamps
+// ---------------------------------------------------------------------------
+
+__global__ void k_path(TreeDev tree, const PlanDev *pl, int32_t max_n, float *out, int32_t *n_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int d = tree.d, W = d + 1;
+    if (pl->inc_f < 0 || pl->inc_b < 0) {
+        *n_out = 0;
+        return;
+    }
+    // chains only point to earlier nodes of the same pool; the cap guards
+    // against a corrupted snapshot
+    int nf = 0;
+    for (int32_t i = pl->inc_f; i >= 0 && nf <= max_n; i = tree.parent[i]) ++nf;
+    int n = 0;
+    if (nf <= max_n) {
+        int j = nf - 1;
+        for (int32_t i = pl->inc_f; i >= 0; i = tree.parent[i], --j)
+            for (int c = 0; c <= d; ++c) out[j * W + c] = tree.x[(int64_t)c * tree.total + i];
+        n = nf;
+        for (int32_t i = pl->inc_b; i >= 0 && n < max_n; i = tree.parent[i], ++n)
+            for (int c = 0; c <= d; ++c) out[n * W + c] = tree.x[(int64_t)c * tree.total + i];
+    }
+    *n_out = n;
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+static int ot_for(int O_pad) {
+    if (O_pad <= 4) return 4;
+    if (O_pad <= 8) return 8;
+    if (O_pad <= 16) return 16;
+    return 32;
+}
+
+template <class F>
+static void dispatch_scene2(const SceneDev &sc, F &&f) {
+    auto by_ot = [&](auto kind, auto obs) {
+        switch (ot_for(sc.O_pad)) {
+            case 4: f(kind, IC<4>{}, obs); break;
+            case 8: f(kind, IC<8>{}, obs); break;
+            case 16: f(kind, IC<16>{}, obs); break;
+            default: f(kind, IC<32>{}, obs); break;
+        }
+    };
+    auto by_obs = [&](auto kind) {
+        if (sc.obs_mode == kObsShared) by_ot(kind, IC<kObsShared>{});
+        else by_ot(kind, IC<kObsGeneric>{});
+    };
+    if (sc.kind == kTranslate) by_obs(IC<kTranslate>{});
+    else by_obs(IC<kDH>{});
+}
+
+template <class T>
+static hipError_t dalloc(T **p, size_t n) {
+    return hipMalloc((void **)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+void work_free(st_problem *p) {
+    Work &w = p->work;
+    void *bufs[] = {w.dir, w.flags, w.grp, w.T, w.qr, w.tr, w.nn_key, w.set_of, w.order, w.tiles, w.n_tiles,
+                    w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit, w.status, w.parent, w.new_idx, w.cost_new,
+                    w.rootT_new, w.br_key, w.br_idx, w.bridge, w.xb, w.br_valid, w.br_free, w.Up, w.Cp};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    memset(&w, 0, sizeof w);
+}
+
+static int max_tiles(int64_t B, int n_sets) { return (int)((B + kScanThreads - 1) / kScanThreads) + n_sets; }
+
+int work_reserve(st_problem *p, int64_t B) {
+    if (p->work.Bcap >= B) return ST_OK;
+    ST_HIP(hipDeviceSynchronize());
+    work_free(p);
+    Work &w = p->work;
+    const int W = p->d + 1;
+    const int mt = max_tiles(B, p->tree.n_pools + 2);
+    w.Bcap = B;
+    ST_HIP(dalloc(&w.dir, B));
+    ST_HIP(dalloc(&w.flags, B));
+    ST_HIP(dalloc(&w.grp, B));
+    ST_HIP(dalloc(&w.T, B));
+    ST_HIP(dalloc(&w.qr, (size_t)B * p->d));
+    ST_HIP(dalloc(&w.tr, B));
+    ST_HIP(dalloc(&w.nn_key, B));
+    ST_HIP(dalloc(&w.set_of, B));
+    ST_HIP(dalloc(&w.order, B));
+    ST_HIP(dalloc(&w.tiles, (size_t)mt * 4));
+    ST_HIP(dalloc(&w.n_tiles, 4));
+    ST_HIP(dalloc(&w.xn, (size_t)B * W));
+    ST_HIP(dalloc(&w.xnew, (size_t)B * W));
+    ST_HIP(dalloc(&w.edge_valid, B));
+    ST_HIP(dalloc(&w.edge_free, B));
+    ST_HIP(dalloc(&w.first_hit, B));
+    ST_HIP(dalloc(&w.status, B));
+    ST_HIP(dalloc(&w.parent, B));
+    ST_HIP(dalloc(&w.new_idx, B));
+    ST_HIP(dalloc(&w.cost_new, B));
+    ST_HIP(dalloc(&w.rootT_new, B));
+    ST_HIP(dalloc(&w.br_key, (size_t)kMaxNch * B));
+    ST_HIP(dalloc(&w.br_idx, (size_t)kMaxNch * B));
+    ST_HIP(dalloc(&w.bridge, B));
+    ST_HIP(dalloc(&w.xb, (size_t)B * W));
+    ST_HIP(dalloc(&w.br_valid, B));
+    ST_HIP(dalloc(&w.br_free, B));
+    ST_HIP(dalloc(&w.Up, B));
+    ST_HIP(dalloc(&w.Cp, B));
+    ST_HIP(hipMemset(w.edge_free, 0, B));
+    ST_HIP(hipMemset(w.br_free, 0, B));
+    return ST_OK;
+}
+
+static int nch_for(int tiles) {
+    int n = 2048 / std::max(tiles, 1);
+    return std::max(1, std::min(kMaxNch, n));
+}
+
+void prof_mark(st_problem *p, int stage, hipStream_t s) {
+    if (!p->prof) return;
+    if (p->prof_used == p->prof_ev.size()) {
+        hipEvent_t ev;
+        if (hipEventCreate(&ev) != hipSuccess) return;
+        p->prof_ev.push_back(ev);
+        p->prof_stage.push_back(0);
+    }
+    p->prof_stage[p->prof_used] = stage;
+    (void)hipEventRecord(p->prof_ev[p->prof_used], s);
+    p->prof_used++;
+}
+
+int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s) {
+    prof_mark(p, kStSample, s);
+    SampleArgs a;
+    a.sc = p->sc;
+    a.win = p->win;
+    a.pl = p->d_plan;
+    a.variant = p->prm.variant;
+    a.N = p->prm.n_groups;
+    a.p_guided = (float)p->prm.p_guided;
+    a.p_new = (float)p->prm.p_new;
+    a.seed = p->prm.seed;
+    a.pid = p->prm.problem_id;
+    a.iter = iter;
+    a.B = B;
+    a.out = out;
+    const int blocks = (int)((B + 255) / 256);
+    const size_t lds = scene_lds_bytes(p->sc);
+    dispatch_scene2(p->sc, [&](auto kind, auto ot, auto obs) {
+        k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+            <<<dim3(blocks), dim3(256), lds, s>>>(a);
+    });
+    ST_HIP(hipGetLastError());
+    return ST_OK;
+}
+
+static int edge_shift(const st_problem *p, bool bridge) {
+    if (bridge) return 6;
+    const double n_typ = p->prm.eta / p->prm.h + 1.0;
+    int shift = 3;
+    while ((1 << shift) < n_typ && shift < 6) ++shift;
+    return shift;
+}
+
+int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s) {
+    int rc = work_reserve(p, B);
+    if (rc != ST_OK) return rc;
+    Work &w = p->work;
+    const int np = p->tree.n_pools;
+    const int d = p->d;
+    // snapshot + buckets for the nearest-node scans (a2)
+    PrepArgs pa;
+    memset(&pa, 0, sizeof pa);
+    pa.pl = p->d_plan;
+    pa.variant = p->prm.variant;
+    pa.n_pools = np;
+    pa.d = d;
+    pa.B = B;
+    pa.s = in;
+    pa.set_of = w.set_of;
+    pa.order = w.order;
+    pa.tiles = (int4 *)w.tiles;
+    pa.n_tiles = w.n_tiles;
+    pa.qbuf = w.xb;  // AoS queries (xb is free until the bridge stage)
+    pa.keys = w.nn_key;
+    pa.mode = 0;
+    prof_mark(p, kStNearest, s);
+    k_prep<<<1, 1024, 0, s>>>(pa);
+    ST_HIP(hipGetLastError());
+    const int mt_nn = max_tiles(B, np);
+    ScanArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.tree = p->tree;
+    sa.pl = p->d_plan;
+    sa.use_snap = 1;
+    sa.variant = p->prm.variant;
+    sa.v = p->sc.v;
+    sa.qbuf = w.xb;
+    sa.order = w.order;
+    sa.tiles = (const int4 *)w.tiles;
+    sa.n_tiles = w.n_tiles;
+    sa.keys = w.nn_key;
+    sa.nch = nch_for(mt_nn);
+    if (p->prm.variant == ST_INTERVAL_ROOT)
+        k_scan<kScanRho><<<dim3(mt_nn, sa.nch), kScanThreads, 0, s>>>(sa);
+    else
+        k_scan<kScanConfig><<<dim3(mt_nn, sa.nch), kScanThreads, 0, s>>>(sa);
+    ST_HIP(hipGetLastError());
+    // steering (a3)
+    SteerArgs ta;
+    ta.sc = p->sc;
+    ta.tree = p->tree;
+    ta.pl = p->d_plan;
+    ta.variant = p->prm.variant;
+    ta.eta = (float)p->prm.eta;
+    ta.B = B;
+    ta.s = in;
+    ta.w = w;
+    const int blocks = (int)((B + 255) / 256);
+    prof_mark(p, kStSteer, s);
+    k_steer<<<blocks, 256, 0, s>>>(ta);
+    ST_HIP(hipGetLastError());
+    // extension edge checks (a4)
+    prof_mark(p, kStEdge, s);
+    ST_HIP(launch_check_edges(p->sc, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit, edge_shift(p, false), s,
+                              p->d_plan->work));
+    prof_mark(p, kStInsert, s);
+    // insertion (a5)
+    InsertArgs ia;
+    ia.sc = p->sc;
+    ia.tree = p->tree;
+    ia.pl = p->d_plan;
+    ia.variant = p->prm.variant;
+    ia.B = B;
+    ia.s = in;
+    ia.w = w;
+    k_insert<<<np, 1024, 0, s>>>(ia);
+    ST_HIP(hipGetLastError());
+    // bridges (a6)
+    pa.mode = 1;
+    pa.status = w.status;
+    pa.dir = in.dir;
+    prof_mark(p, kStBridgeSel, s);
+    k_prep<<<1, 1024, 0, s>>>(pa);
+    ST_HIP(hipGetLastError());
+    const int mt_br = max_tiles(B, 2);
+    ScanArgs sb = sa;
+    sb.qbuf = w.xnew;
+    sb.keys = nullptr;
+    sb.pkey = w.br_key;
+    sb.pidx = w.br_idx;
+    sb.pstride = B;
+    sb.nch = nch_for(mt_br);
+    k_scan<kScanBridge><<<dim3(mt_br, sb.nch), kScanThreads, 0, s>>>(sb);
+    ST_HIP(hipGetLastError());
+    BridgeArgs ba;
+    ba.tree = p->tree;
+    ba.B = B;
+    ba.nch = sb.nch;
+    ba.dir = in.dir;
+    ba.w = w;
+    k_bridge_merge<<<blocks, 256, 0, s>>>(ba);
+    ST_HIP(hipGetLastError());
+    prof_mark(p, kStBridgeEdge, s);
+    ST_HIP(launch_check_edges(p->sc, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true), s,
+                              p->d_plan->work + 2));
+    prof_mark(p, kStPublish, s);
+    // publish (a7)
+    PublishArgs pb;
+    pb.pl = p->d_plan;
+    pb.B = B;
+    pb.dir = in.dir;
+    pb.w = w;
+    if (out) pb.out = *out;
+    else memset(&pb.out, 0, sizeof pb.out);
+    k_publish<<<1, 1024, 0, s>>>(pb);
+    ST_HIP(hipGetLastError());
+    if (out && out->xnew) {
+        XnewOutArgs xa{B, d, w.status, w.xnew, out->xnew};
+        k_xnew_out<<<blocks, 256, 0, s>>>(xa);
+        ST_HIP(hipGetLastError());
+    }
+    // allocation update (a8 / a9)
+    RootsArgs ra;
+    ra.sc = p->sc;
+    ra.tree = p->tree;
+    ra.win = p->win;
+    ra.pl = p->d_plan;
+    ra.variant = p->prm.variant;
+    ra.N = p->prm.n_groups;
+    k_roots<<<1, 256, 0, s>>>(ra);
+    ST_HIP(hipGetLastError());
+    prof_mark(p, kStEnd, s);
+    return ST_OK;
+}
+
+int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64_t M, const float *xq,
+                int32_t *idx_out, float *dist_out, hipStream_t s) {
+    if (M <= 0) return ST_OK;
+    int rc = work_reserve(p, M);
+    if (rc != ST_OK) return rc;
+    Work &w = p->work;
+    const int nt = (int)((M + kScanThreads - 1) / kScanThreads);
+    k_fill_tiles<<<(nt + 255) / 256, 256, 0, s>>>(M, set < 0 ? (set == ST_SET_FORWARD ? 0 : kSetAllBackward) : 1 + set,
+                                                 sigma, (int4 *)w.tiles, w.n_tiles, w.nn_key);
+    ST_HIP(hipGetLastError());
+    ScanArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.tree = p->tree;
+    sa.pl = p->d_plan;
+    sa.use_snap = 0;
+    sa.variant = p->prm.variant;
+    sa.v = p->sc.v;
+    sa.qbuf = xq;
+    sa.order = nullptr;
+    sa.tiles = (const int4 *)w.tiles;
+    sa.n_tiles = w.n_tiles;
+    sa.keys = w.nn_key;
+    sa.nch = nch_for(nt);
+    if (metric == ST_METRIC_RHO) k_scan<kScanRho><<<dim3(nt, sa.nch), kScanThreads, 0, s>>>(sa);
+    else k_scan<kScanConfig><<<dim3(nt, sa.nch), kScanThreads, 0, s>>>(sa);
+    ST_HIP(hipGetLastError());
+    k_nn_out<<<(int)((M + 255) / 256), 256, 0, s>>>(M, metric, w.nn_key, idx_out, dist_out);
+    ST_HIP(hipGetLastError());
+    return ST_OK;
+}
+
+static st_samples work_samples(st_problem *p) {
+    Work &w = p->work;
+    st_samples s;
+    s.dir = w.dir;
+    s.flags = w.flags;
+    s.grp = w.grp;
+    s.T = w.T;
+    s.qr = w.qr;
+    s.tr = w.tr;
+    return s;
+}
+
+static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
+    const int64_t B = p->prm.batch;
+    int rc = work_reserve(p, B);
+    if (rc != ST_OK) return rc;
+    const st_samples smp = work_samples(p);
+    for (int64_t i = 0; i < iters; ++i) {
+        if ((rc = sample_batch(p, p->iter, B, smp, s)) != ST_OK) return rc;
+        if ((rc = extend_batch(p, B, smp, nullptr, s)) != ST_OK) return rc;
+        p->iter++;
+    }
+    return ST_OK;
+}
+
+}  // namespace st
+
+using namespace st;
+
+extern "C" {
+
+int st_nearest(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64_t M, const float *xq,
+               int32_t *idx_out, float *dist_out, void *stream) {
+    if (!p || M < 0 || (M > 0 && (!xq || !idx_out))) {
+        set_error("st_nearest: bad arguments");
+        return ST_EINVAL;
+    }
+    if (metric != ST_METRIC_RHO && metric != ST_METRIC_CONFIG) {
+        set_error("st_nearest: unknown metric %d", metric);
+        return ST_EINVAL;
+    }
+    if (sigma != 1 && sigma != -1) {
+        set_error("st_nearest: sigma must be +1 or -1");
+        return ST_EINVAL;
+    }
+    if (set != ST_SET_FORWARD && set != ST_SET_ALL_BACKWARD && (set < 0 || set >= p->prm.n_groups)) {
+        set_error("st_nearest: unknown set %d", set);
+        return ST_EINVAL;
+    }
+    return nearest_set(p, set, metric, sigma, M, xq, idx_out, dist_out, (hipStream_t)stream);
+}
+
+int st_sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples *out, void *stream) {
+    if (!p || !out || B < 0 || (B > 0 && (!out->dir || !out->flags || !out->grp || !out->T || !out->qr || !out->tr))) {
+        set_error("st_sample_batch: bad arguments");
+        return ST_EINVAL;
+    }
+    if (B == 0) return ST_OK;
+    return sample_batch(p, iter, B, *out, (hipStream_t)stream);
+}
+
+int st_extend_batch(st_problem *p, int64_t B, const st_samples *s, const st_extend_out *o, void *stream) {
+    if (!p || !s || B < 0 || (B > 0 && (!s->dir || !s->flags || !s->grp || !s->T || !s->qr || !s->tr))) {
+        set_error("st_extend_batch: bad arguments");
+        return ST_EINVAL;
+    }
+    if (B == 0) return ST_OK;
+    int rc = extend_batch(p, B, *s, o, (hipStream_t)stream);
+    if (rc == ST_OK) p->iter++;
+    return rc;
+}
+
+int st_iterate(st_problem *p, int64_t iters, void *stream) {
+    if (!p || iters < 0) {
+        set_error("st_iterate: bad arguments");
+        return ST_EINVAL;
+    }
+    return iterate(p, iters, (hipStream_t)stream);
+}
+
+int st_plan(st_problem *p, const st_budget *b, st_path *out) {
+    if (!p || !b || !out) {
+        set_error("st_plan: bad arguments");
+        return ST_EINVAL;
+    }
+    memset(out, 0, sizeof *out);
+    out->dof = p->d;
+    out->first_solution_iter = -1;
+    out->arrival = INFINITY;
+    out->length = INFINITY;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    const int d = p->d, W = d + 1;
+    // trivial case: q_s = q_g with a free start, arrival at time 0 allowed
+    bool same = true;
+    for (int j = 0; j < d; ++j) same = same && p->q_s[j] == p->q_g[j];
+    float *dx = nullptr;
+    uint8_t *dfree = nullptr;
+    ST_HIP(hipMalloc((void **)&dx, W * sizeof(float)));
+    ST_HIP(hipMalloc((void **)&dfree, 1));
+    std::vector<float> xs(W);
+    for (int j = 0; j < d; ++j) xs[j] = (float)p->q_s[j];
+    xs[d] = 0.f;
+    ST_HIP(hipMemcpy(dx, xs.data(), W * sizeof(float), hipMemcpyHostToDevice));
+    ST_HIP(launch_check_states(p->sc, 1, dx, dfree, 0));
+    uint8_t start_free = 0;
+    ST_HIP(hipMemcpy(&start_free, dfree, 1, hipMemcpyDeviceToHost));
+    (void)hipFree(dx);
+    (void)hipFree(dfree);
+    if (same && start_free && p->L <= 0.0) {
+        out->n_states = 1;
+        out->states = (double *)malloc(sizeof(double) * W);
+        for (int j = 0; j < d; ++j) out->states[j] = p->q_s[j];
+        out->states[d] = 0.0;
+        out->arrival = 0.0;
+        out->length = 0.0;
+        out->total_ms = ms_since();
+        return ST_TRIVIAL;
+    }
+    if (!start_free) {
+        out->total_ms = ms_since();
+        return ST_NO_SOLUTION;
+    }
+    hipStream_t s = nullptr;
+    ST_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    PlanDev *host = nullptr;
+    ST_HIP(hipHostMalloc((void **)&host, sizeof(PlanDev), hipHostMallocDefault));
+    const int chunk = b->iters_per_sync > 0 ? b->iters_per_sync : 8;
+    int64_t done_iters = 0;
+    int rc = ST_OK;
+    while (true) {
+        int64_t n = chunk;
+        if (b->max_iters > 0) n = std::min<int64_t>(n, b->max_iters - done_iters);
+        if (n <= 0) break;
+        if ((rc = iterate(p, n, s)) != ST_OK) break;
+        done_iters += n;
+        if (hipMemcpyAsync(host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("st_plan: device synchronisation failed");
+            rc = ST_EHIP;
+            break;
+        }
+        if (host->first_iter >= 0 && out->first_solution_iter < 0) {
+            out->first_solution_iter = host->first_iter;
+            out->first_solution_ms = ms_since();
+        }
+        if (host->done) break;
+        if (b->stop_at_first && host->first_iter >= 0) break;
+        if (b->max_ms > 0 && ms_since() >= b->max_ms) break;
+        if (b->max_iters <= 0 && b->max_ms <= 0 && !b->stop_at_first) break;
+    }
+    if (rc == ST_OK) {
+        const int32_t max_n = 1 << 16;
+        float *dpath = nullptr;
+        int32_t *dn = nullptr;
+        if (hipMalloc((void **)&dpath, (size_t)max_n * W * sizeof(float)) != hipSuccess ||
+            hipMalloc((void **)&dn, sizeof(int32_t)) != hipSuccess) {
+            set_error("st_plan: out of device memory");
+            rc = ST_ENOMEM;
+        } else {
+            k_path<<<1, 1, 0, s>>>(p->tree, p->d_plan, max_n, dpath, dn);
+            int32_t n = 0;
+            (void)hipMemcpyAsync(&n, dn, sizeof n, hipMemcpyDeviceToHost, s);
+            (void)hipMemcpyAsync(host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s);
+            (void)hipStreamSynchronize(s);
+            std::vector<float> buf((size_t)std::max(n, 1) * W);
+            if (n > 0) (void)hipMemcpy(buf.data(), dpath, (size_t)n * W * sizeof(float), hipMemcpyDeviceToHost);
+            out->iterations = p->iter;
+            out->arrival = host->U;
+            out->length = host->C;
+            if (n > 0) {
+                out->n_states = n;
+                out->states = (double *)malloc(sizeof(double) * (size_t)n * W);
+                for (size_t i = 0; i < (size_t)n * W; ++i) out->states[i] = buf[i];
+            }
+            rc = n > 0 ? ST_OK : ST_NO_SOLUTION;
+        }
+        if (dpath) (void)hipFree(dpath);
+        if (dn) (void)hipFree(dn);
+    }
+    (void)hipHostFree(host);
+    (void)hipStreamDestroy(s);
+    out->total_ms = ms_since();
+    return rc;
+}
+
+int st_profile_enable(st_problem *p, int32_t enable) {
+    if (!p) {
+        set_error("st_profile_enable: null problem");
+        return ST_EINVAL;
+    }
+    ST_HIP(hipDeviceSynchronize());
+    p->prof = enable != 0;
+    p->prof_used = 0;
+    return ST_OK;
+}
+
+int st_profile_read(st_problem *p, double *ms, int64_t *marks) {
+    if (!p || !ms) {
+        set_error("st_profile_read: bad arguments");
+        return ST_EINVAL;
+    }
+    ST_HIP(hipDeviceSynchronize());
+    for (int i = 0; i < ST_PROFILE_STAGES; ++i) {
+        ms[i] = 0.0;
+        if (marks) marks[i] = 0;
+    }
+    // the interval between consecutive marks belongs to the earlier mark's stage
+    for (size_t i = 0; i + 1 < p->prof_used; ++i) {
+        const int st_ = p->prof_stage[i];
+        if (st_ == kStEnd) continue;
+        float t = 0.f;
+        ST_HIP(hipEventElapsedTime(&t, p->prof_ev[i], p->prof_ev[i + 1]));
+        ms[st_] += t;
+        if (marks) marks[st_]++;
+    }
+    p->prof_used = 0;
+    return ST_OK;
+}
+
+int st_work_counters(st_problem *p, uint64_t *out) {
+    if (!p || !out) {
+        set_error("st_work_counters: bad arguments");
+        return ST_EINVAL;
+    }
+    ST_HIP(hipDeviceSynchronize());
+    PlanDev pl;
+    ST_HIP(hipMemcpy(&pl, p->d_plan, sizeof pl, hipMemcpyDeviceToHost));
+    for (int i = 0; i < 4; ++i) out[i] = pl.work[i];
+    return ST_OK;
+}
+
+void st_path_free(st_path *path) {
+    if (!path) return;
+    free(path->states);
+    path->states = nullptr;
+    path->n_states = 0;
+}
+
+}  // extern "C"

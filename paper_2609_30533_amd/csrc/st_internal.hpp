@@ -1,0 +1,172 @@
+// st_internal.hpp -- host-side problem object, device planner state and the
+// kernel launchers shared by the translation units of the library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/st.h"
+#include "st_device.hpp"
+
+namespace st {
+
+void set_error(const char *fmt, ...);
+
+#define ST_HIP(call)                                                                                     \
+    do {                                                                                                 \
+        hipError_t e_ = (call);                                                                          \
+        if (e_ != hipSuccess) {                                                                          \
+            ::st::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return ST_EHIP;                                                                              \
+        }                                                                                                \
+    } while (0)
+
+constexpr int kMaxGroups = ST_MAX_GROUPS;
+constexpr int kMaxPools = kMaxGroups + 1;
+
+// Planner state that lives in device memory (one record per problem).
+struct PlanDev {
+    float U, C;               // incumbent (arrival first, length breaks ties)
+    int32_t inc_f, inc_b;     // incumbent endpoints (global node indices)
+    int32_t improved;         // last batch: 0 none, 1 equal-U improvement, 2 strict drop of U
+    int32_t done;             // interval root: L >= min(H, U)
+    int32_t first_iter;       // iteration of the first incumbent (-1)
+    int32_t overflow;         // an insert was dropped for capacity
+    int32_t iter;             // iterations run so far
+    int32_t n_active;         // recycling: active slots
+    double Ubar;              // interval root: min(H, U)
+    double G;                 // interval root: guided length below Ubar
+    int32_t jstar;            // interval root: windows starting below Ubar
+    int32_t pad0;
+    float U_snap;             // U at the start of the current batch
+    int32_t pad1;
+    int32_t count[kMaxPools];       // nodes per pool
+    int32_t count_snap[kMaxPools];  // nodes per pool at the start of the current batch
+    float minRootT[kMaxGroups];     // interval root: earliest root time of the group's trees
+    float slotT[kMaxGroups];        // recycling: root time per slot (inf when empty)
+    int32_t slot_active[kMaxGroups];
+    uint32_t slot_gen[kMaxGroups];
+    int32_t slotK[kMaxGroups];      // goal-grid index of the slot's root
+    int32_t active_list[kMaxGroups];
+    // work counters: [0] extension edges decided, [1] their states up to the
+    // first hit (n+1 when free), [2] bridge edges decided, [3] their states
+    unsigned long long work[4];
+};
+
+// Node pools in device memory, SoA.
+struct TreeDev {
+    float *x;          // [d+1][total]
+    int32_t *parent;   // [total]
+    float *cost;       // [total]
+    float *rootT;      // [total]
+    int64_t total;
+    int32_t cap_fwd, cap_bwd, n_pools, d;
+};
+
+__host__ __device__ inline int64_t pool_base(const TreeDev &t, int p) {
+    return p == 0 ? 0 : (int64_t)t.cap_fwd + (int64_t)(p - 1) * t.cap_bwd;
+}
+__host__ __device__ inline int32_t pool_cap(const TreeDev &t, int p) { return p == 0 ? t.cap_fwd : t.cap_bwd; }
+
+// Interval-root guided windows (merged, clipped to [L, H]).
+struct WindowsDev {
+    const double *lo, *hi, *cum;  // cum[j] = total length of windows 0..j-1
+    int32_t nw;
+    int32_t pad;
+    double L, H, dt;
+    int32_t N;
+    int32_t k_lo, k_hi;
+    const uint8_t *gfree;         // goal grid, [k_hi - k_lo + 1]
+};
+
+// Per-batch work buffers (capacity Bcap workers).
+struct Work {
+    int64_t Bcap;
+    // samples (owned copy used by st_iterate)
+    int8_t *dir;
+    uint8_t *flags;
+    int32_t *grp;
+    float *T, *qr, *tr;
+    // extension
+    unsigned long long *nn_key;  // [B] packed (distance bits, node index)
+    int32_t *set_of;             // [B] nearest-node set (pool) or -1
+    int32_t *order;              // [B] workers grouped by set
+    int32_t *tiles;              // [3 * max_tiles]: set, first, count
+    int32_t *n_tiles;            // [2]
+    float *xn, *xnew;            // [B][d+1]
+    uint8_t *edge_valid, *edge_free;
+    int32_t *first_hit;          // [B] scratch for the edge checks
+    int8_t *status;
+    int32_t *parent, *new_idx;
+    float *cost_new, *rootT_new;
+    // bridges
+    unsigned long long *br_key;  // [NCH][B]
+    int32_t *br_idx;             // [NCH][B]
+    int32_t *bridge;
+    float *xb;                   // [B][d+1]
+    uint8_t *br_valid, *br_free;
+    float *Up, *Cp;
+};
+
+}  // namespace st
+
+struct st_problem {
+    int device = 0;
+    st_params prm{};
+    int d = 0, kind = 0, S = 0, O = 0;
+    std::vector<double> q_lo, q_hi, q_s, q_g;
+    double t_min = 0, t_max = 0, v_max = 0, Lg = 0, L = 0;
+    st::SceneDev sc{};
+    float4 *d_sph = nullptr;
+    float *d_R2 = nullptr;
+    float4 *d_seg = nullptr;
+    float *d_segt = nullptr;
+    // goal grid and windows
+    int64_t k_lo = 0, k_hi = -1;
+    uint8_t *d_gfree = nullptr;
+    std::vector<uint8_t> h_gfree;
+    std::vector<double> h_wlo, h_whi, h_wcum;
+    double *d_wlo = nullptr, *d_whi = nullptr, *d_wcum = nullptr;
+    st::WindowsDev win{};
+    // trees and planner state
+    st::TreeDev tree{};
+    st::PlanDev *d_plan = nullptr;
+    st::Work work{};
+    int64_t iter = 0;
+    int nch = 16;  // node chunks per query tile in scans
+    // optional stage timing with HIP events (stage id per recorded event)
+    bool prof = false;
+    std::vector<hipEvent_t> prof_ev;
+    std::vector<int> prof_stage;
+    size_t prof_used = 0;
+};
+
+namespace st {
+
+// ---- collision ------------------------------------------------------------
+size_t scene_lds_bytes(const SceneDev &sc);
+hipError_t launch_check_states(const SceneDev &sc, int64_t M, const float *x, uint8_t *free_out, hipStream_t s);
+// Lanes per edge = 1 << lpe_shift (1..64).  first_hit may be null (any-hit exit).
+hipError_t launch_check_edges(const SceneDev &sc, int64_t E, const float *xa, const float *xb, const uint8_t *valid,
+                              uint8_t *free_out, int32_t *first_hit, int lpe_shift, hipStream_t s,
+                              unsigned long long *work = nullptr);
+
+// ---- stage timing ------------------------------------------------------------
+enum Stage { kStSample = 0, kStNearest, kStSteer, kStEdge, kStInsert, kStBridgeSel, kStBridgeEdge, kStPublish,
+             kStEnd, kNumStages };
+void prof_mark(st_problem *p, int stage, hipStream_t s);
+
+// ---- nearest node and the extension pipeline --------------------------------
+int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64_t M, const float *xq,
+                int32_t *idx_out, float *dist_out, hipStream_t s);
+int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s);
+int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s);
+int work_reserve(st_problem *p, int64_t B);
+void work_free(st_problem *p);
+
+// ---- allocation ------------------------------------------------------------
+hipError_t launch_roots_update(st_problem *p, hipStream_t s);
+
+}  // namespace st

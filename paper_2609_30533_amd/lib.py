@@ -1,0 +1,360 @@
+"""Thin ctypes binding of the C ABI in include/st.h.
+
+Argument marshalling only: every step of the planner runs in the HIP kernels
+of libstprrtc.so.  PyTorch supplies device memory (tensor.data_ptr()) and the
+stream (torch.cuda.current_stream().cuda_stream).  If the library has not been
+built, every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import scenes
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_build", "libstprrtc.so")
+
+ST_OK, ST_NO_SOLUTION, ST_TRIVIAL = 0, 1, 2
+SET_FORWARD, SET_ALL_BACKWARD = -1, -2
+METRIC_RHO, METRIC_CONFIG = 0, 1
+FLAG_SKIP, FLAG_USE_NEW = 1, 2
+STATUS_SKIPPED, STATUS_TRAPPED, STATUS_ADVANCED, STATUS_DROPPED = 0, 1, 2, 3
+
+
+class StError(RuntimeError):
+    pass
+
+
+class Params(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("n_groups", C.c_int32), ("batch", C.c_int32),
+                ("eta", C.c_double), ("h", C.c_double), ("dt", C.c_double),
+                ("p_new", C.c_double), ("p_guided", C.c_double),
+                ("cap_fwd", C.c_int32), ("cap_bwd", C.c_int32),
+                ("seed", C.c_uint32), ("problem_id", C.c_uint32)]
+
+
+class Desc(C.Structure):
+    _fields_ = [("dof", C.c_int32), ("robot_kind", C.c_int32), ("dh", C.POINTER(C.c_double)),
+                ("n_spheres", C.c_int32), ("sphere_link", C.POINTER(C.c_int32)), ("spheres", C.POINTER(C.c_double)),
+                ("q_lo", C.POINTER(C.c_double)), ("q_hi", C.POINTER(C.c_double)),
+                ("q_start", C.POINTER(C.c_double)), ("q_goal", C.POINTER(C.c_double)),
+                ("t_min", C.c_double), ("t_max", C.c_double), ("v_max", C.c_double),
+                ("n_obstacles", C.c_int32), ("max_waypoints", C.c_int32),
+                ("n_waypoints", C.POINTER(C.c_int32)), ("waypoints", C.POINTER(C.c_double)),
+                ("obstacle_radius", C.POINTER(C.c_double)), ("params", Params)]
+
+
+class Samples(C.Structure):
+    _fields_ = [("dir", C.c_void_p), ("flags", C.c_void_p), ("grp", C.c_void_p), ("T", C.c_void_p),
+                ("qr", C.c_void_p), ("tr", C.c_void_p)]
+
+
+class ExtendOut(C.Structure):
+    _fields_ = [("status", C.c_void_p), ("parent", C.c_void_p), ("new_idx", C.c_void_p), ("xnew", C.c_void_p),
+                ("bridge", C.c_void_p), ("bridge_ok", C.c_void_p), ("Up", C.c_void_p), ("Cp", C.c_void_p)]
+
+
+class Budget(C.Structure):
+    _fields_ = [("max_iters", C.c_int64), ("max_ms", C.c_double), ("stop_at_first", C.c_int32),
+                ("iters_per_sync", C.c_int32)]
+
+
+class Path(C.Structure):
+    _fields_ = [("n_states", C.c_int64), ("dof", C.c_int32), ("states", C.POINTER(C.c_double)),
+                ("arrival", C.c_double), ("length", C.c_double), ("iterations", C.c_int64),
+                ("first_solution_iter", C.c_int64), ("first_solution_ms", C.c_double), ("total_ms", C.c_double)]
+
+
+class Info(C.Structure):
+    _fields_ = [("U", C.c_double), ("C", C.c_double), ("inc_fwd", C.c_int64), ("inc_bwd", C.c_int64),
+                ("L", C.c_double), ("H", C.c_double), ("k_lo", C.c_int64), ("k_hi", C.c_int64),
+                ("iter", C.c_int64), ("overflow", C.c_int32), ("n_active", C.c_int32), ("total_cap", C.c_int64),
+                ("n_pools", C.c_int32), ("first_iter", C.c_int64)]
+
+
+# Every symbol the header declares (used by the load test).
+EXPORTS = [
+    "st_problem_create", "st_problem_destroy", "st_problem_reset", "st_check_states", "st_check_edges",
+    "st_nearest", "st_sample_batch", "st_extend_batch", "st_iterate", "st_plan", "st_path_free", "st_get_info",
+    "st_tree_export", "st_tree_import", "st_slots_export", "st_goal_grid_export", "st_partition_export",
+    "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
+]
+STAGES = ["sample", "nearest", "steer", "edge_check", "insert", "bridge_select", "bridge_check", "publish"]
+
+_lib = None
+
+
+def load():
+    """Load the built library; raise if it is missing (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise StError("libstprrtc.so is not built (run __graft_entry__.build()); there is no CPU fallback")
+    # PyTorch ships its own HIP runtime with the same soname; loading it first
+    # makes this library bind to that one runtime instead of a second copy.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i64, i32, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_double
+    L.st_problem_create.argtypes = [C.POINTER(Desc), C.POINTER(vp)]
+    L.st_problem_destroy.argtypes = [vp]
+    L.st_problem_destroy.restype = None
+    L.st_problem_reset.argtypes = [vp]
+    L.st_check_states.argtypes = [vp, i64, vp, vp, vp]
+    L.st_check_edges.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.st_nearest.argtypes = [vp, i32, i32, i32, i64, vp, vp, vp, vp]
+    L.st_sample_batch.argtypes = [vp, i64, i64, C.POINTER(Samples), vp]
+    L.st_extend_batch.argtypes = [vp, i64, C.POINTER(Samples), C.POINTER(ExtendOut), vp]
+    L.st_iterate.argtypes = [vp, i64, vp]
+    L.st_plan.argtypes = [vp, C.POINTER(Budget), C.POINTER(Path)]
+    L.st_path_free.argtypes = [C.POINTER(Path)]
+    L.st_path_free.restype = None
+    L.st_get_info.argtypes = [vp, C.POINTER(Info)]
+    L.st_tree_export.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.st_tree_import.argtypes = [vp, vp, vp, vp, vp, vp, dbl, dbl, i64, i64, i64, vp, vp, vp, vp]
+    L.st_slots_export.argtypes = [vp, vp, vp, vp, vp]
+    L.st_goal_grid_export.argtypes = [vp, vp]
+    L.st_partition_export.argtypes = [vp, vp, vp, vp, i32]
+    L.st_profile_enable.argtypes = [vp, i32]
+    L.st_profile_read.argtypes = [vp, vp, vp]
+    L.st_work_counters.argtypes = [vp, vp]
+    L.st_last_error.argtypes = []
+    L.st_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("st_problem_destroy", "st_path_free", "st_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise StError("%s failed (%d): %s" % (what, rc, load().st_last_error().decode()))
+    return rc
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t):
+    """Device pointer of a contiguous torch tensor (None for None)."""
+    if t is None:
+        return None
+    assert t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+class Problem:
+    """One planning problem on the current HIP device."""
+
+    def __init__(self, prob: scenes.Problem, problem_id: int = 0):
+        self.L = load()
+        self.prob = prob
+        self.d = prob.d
+        self.N = prob.params.n_groups
+        keep = []
+
+        def arr(a, dt):
+            a = np.ascontiguousarray(a, dtype=dt)
+            keep.append(a)
+            return a.ctypes.data_as(C.POINTER(C.c_double if dt == np.float64 else C.c_int32))
+
+        D = Desc()
+        D.dof, D.robot_kind = prob.d, prob.kind
+        D.dh = arr(prob.dh, np.float64)
+        D.n_spheres = prob.n_spheres
+        D.sphere_link = arr(prob.sphere_link, np.int32)
+        D.spheres = arr(prob.sphere, np.float64)
+        D.q_lo, D.q_hi = arr(prob.q_lo, np.float64), arr(prob.q_hi, np.float64)
+        D.q_start, D.q_goal = arr(prob.q_start, np.float64), arr(prob.q_goal, np.float64)
+        D.t_min, D.t_max, D.v_max = prob.t_min, prob.t_max, prob.v_max
+        D.n_obstacles, D.max_waypoints = prob.n_obs, max(prob.w_max, 1)
+        D.n_waypoints = arr(prob.n_wp, np.int32)
+        D.waypoints = arr(prob.wp, np.float64)
+        D.obstacle_radius = arr(prob.obs_r, np.float64)
+        p = prob.params
+        D.params = Params(p.variant, p.n_groups, p.batch, p.eta, p.h, p.dt, p.p_new, p.p_guided, p.cap_fwd,
+                          p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF)
+        h = C.c_void_p()
+        _check(self.L.st_problem_create(C.byref(D), C.byref(h)), "st_problem_create")
+        self.h = h
+        del keep
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.st_problem_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- collision ----------------------------------------------------------
+    def check_states(self, x, out=None, stream=None):
+        import torch
+        M = x.shape[0]
+        out = out if out is not None else torch.empty(M, dtype=torch.uint8, device=x.device)
+        _check(self.L.st_check_states(self.h, M, _dptr(x), _dptr(out), _stream(stream)), "st_check_states")
+        return out
+
+    def check_edges(self, xa, xb, first_hit=True, stream=None):
+        import torch
+        E = xa.shape[0]
+        free = torch.empty(E, dtype=torch.uint8, device=xa.device)
+        fh = torch.empty(E, dtype=torch.int32, device=xa.device) if first_hit else None
+        _check(self.L.st_check_edges(self.h, E, _dptr(xa), _dptr(xb), _dptr(free), _dptr(fh), _stream(stream)),
+               "st_check_edges")
+        return free, fh
+
+    # ---- nearest ------------------------------------------------------------
+    def nearest(self, xq, set_id=SET_FORWARD, metric=METRIC_RHO, sigma=1, stream=None):
+        import torch
+        M = xq.shape[0]
+        idx = torch.empty(M, dtype=torch.int32, device=xq.device)
+        dist = torch.empty(M, dtype=torch.float32, device=xq.device)
+        _check(self.L.st_nearest(self.h, set_id, metric, sigma, M, _dptr(xq), _dptr(idx), _dptr(dist),
+                                 _stream(stream)), "st_nearest")
+        return idx, dist
+
+    # ---- batches ------------------------------------------------------------
+    def alloc_samples(self, B, device="cuda"):
+        import torch
+        return dict(dir=torch.zeros(B, dtype=torch.int8, device=device),
+                    flags=torch.zeros(B, dtype=torch.uint8, device=device),
+                    grp=torch.zeros(B, dtype=torch.int32, device=device),
+                    T=torch.zeros(B, dtype=torch.float32, device=device),
+                    qr=torch.zeros(self.d, B, dtype=torch.float32, device=device),
+                    tr=torch.zeros(B, dtype=torch.float32, device=device))
+
+    @staticmethod
+    def _samples_struct(s):
+        return Samples(*[_dptr(s[k]) for k in ("dir", "flags", "grp", "T", "qr", "tr")])
+
+    def sample(self, it, B=None, stream=None):
+        B = B or self.prob.params.batch
+        s = self.alloc_samples(B)
+        S = self._samples_struct(s)
+        _check(self.L.st_sample_batch(self.h, it, B, C.byref(S), _stream(stream)), "st_sample_batch")
+        return s
+
+    def extend(self, s, stream=None):
+        import torch
+        B = s["dir"].shape[0]
+        dev = s["dir"].device
+        o = dict(status=torch.zeros(B, dtype=torch.int8, device=dev),
+                 parent=torch.zeros(B, dtype=torch.int32, device=dev),
+                 new_idx=torch.zeros(B, dtype=torch.int32, device=dev),
+                 xnew=torch.zeros(self.d + 1, B, dtype=torch.float32, device=dev),
+                 bridge=torch.zeros(B, dtype=torch.int32, device=dev),
+                 bridge_ok=torch.zeros(B, dtype=torch.uint8, device=dev),
+                 Up=torch.zeros(B, dtype=torch.float32, device=dev),
+                 Cp=torch.zeros(B, dtype=torch.float32, device=dev))
+        S = self._samples_struct(s)
+        O = ExtendOut(*[_dptr(o[k]) for k in ("status", "parent", "new_idx", "xnew", "bridge", "bridge_ok", "Up",
+                                              "Cp")])
+        _check(self.L.st_extend_batch(self.h, B, C.byref(S), C.byref(O), _stream(stream)), "st_extend_batch")
+        return o
+
+    def iterate(self, iters, stream=None):
+        _check(self.L.st_iterate(self.h, iters, _stream(stream)), "st_iterate")
+
+    def plan(self, max_iters=0, max_ms=0.0, stop_at_first=False, iters_per_sync=0):
+        b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
+        path = Path()
+        rc = _check(self.L.st_plan(self.h, C.byref(b), C.byref(path)), "st_plan")
+        try:
+            n = path.n_states
+            states = np.ctypeslib.as_array(path.states, shape=(n * (self.d + 1),)).reshape(n, self.d + 1).copy() \
+                if n > 0 else None
+            res = dict(rc=rc, states=states, U=path.arrival, C=path.length, iterations=path.iterations,
+                       first_iter=path.first_solution_iter, first_ms=path.first_solution_ms, total_ms=path.total_ms)
+        finally:
+            self.L.st_path_free(C.byref(path))
+        return res
+
+    def reset(self):
+        _check(self.L.st_problem_reset(self.h), "st_problem_reset")
+
+    # ---- state I/O ----------------------------------------------------------
+    def info(self):
+        inf = Info()
+        _check(self.L.st_get_info(self.h, C.byref(inf)), "st_get_info")
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    def export(self):
+        inf = self.info()
+        tot = inf["total_cap"]
+        counts = np.zeros(1 + self.N, dtype=np.int64)
+        x = np.zeros((tot, self.d + 1), dtype=np.float32)
+        par = np.zeros(tot, dtype=np.int32)
+        cost = np.zeros(tot, dtype=np.float32)
+        rootT = np.zeros(tot, dtype=np.float32)
+        _check(self.L.st_tree_export(self.h, _ptr(counts), _ptr(x), _ptr(par), _ptr(cost), _ptr(rootT)),
+               "st_tree_export")
+        return dict(counts=counts, x=x, parent=par, cost=cost, rootT=rootT)
+
+    def import_state(self, counts, x, parent, cost, rootT, U, Cst, inc_f, inc_b, it, slots=None):
+        counts = np.ascontiguousarray(counts, dtype=np.int64)
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        parent = np.ascontiguousarray(parent, dtype=np.int32)
+        cost = np.ascontiguousarray(cost, dtype=np.float32)
+        rootT = np.ascontiguousarray(rootT, dtype=np.float32)
+        if slots is not None:
+            sT = np.ascontiguousarray(slots[0], dtype=np.float64)
+            sa = np.ascontiguousarray(slots[1], dtype=np.int32)
+            sg = np.ascontiguousarray(slots[2], dtype=np.uint32)
+            sk = np.ascontiguousarray(slots[3], dtype=np.int64)
+            sp = [_ptr(sT), _ptr(sa), _ptr(sg), _ptr(sk)]
+        else:
+            sp = [None] * 4
+        _check(self.L.st_tree_import(self.h, _ptr(counts), _ptr(x), _ptr(parent), _ptr(cost), _ptr(rootT), float(U),
+                                     float(Cst), int(inc_f), int(inc_b), int(it), *sp), "st_tree_import")
+
+    def profile(self, enable=True):
+        _check(self.L.st_profile_enable(self.h, 1 if enable else 0), "st_profile_enable")
+
+    def profile_read(self):
+        ms = np.zeros(9)
+        marks = np.zeros(9, dtype=np.int64)
+        _check(self.L.st_profile_read(self.h, _ptr(ms), _ptr(marks)), "st_profile_read")
+        return {name: (float(ms[i]), int(marks[i])) for i, name in enumerate(STAGES)}
+
+    def work_counters(self):
+        out = np.zeros(4, dtype=np.uint64)
+        _check(self.L.st_work_counters(self.h, _ptr(out)), "st_work_counters")
+        return dict(edges=int(out[0]), edge_states=int(out[1]), bridges=int(out[2]), bridge_states=int(out[3]))
+
+    def slots(self):
+        T = np.zeros(self.N)
+        a = np.zeros(self.N, dtype=np.int32)
+        g = np.zeros(self.N, dtype=np.uint32)
+        k = np.zeros(self.N, dtype=np.int64)
+        _check(self.L.st_slots_export(self.h, _ptr(T), _ptr(a), _ptr(g), _ptr(k)), "st_slots_export")
+        return T, a, g, k
+
+    def goal_free(self):
+        inf = self.info()
+        n = inf["k_hi"] - inf["k_lo"] + 1
+        out = np.zeros(max(n, 1), dtype=np.uint8)
+        _check(self.L.st_goal_grid_export(self.h, _ptr(out)), "st_goal_grid_export")
+        return out[:max(n, 0)]
+
+    def partition(self, maxp=4096):
+        I = np.zeros(2 * self.N)
+        npc = np.zeros(self.N, dtype=np.int32)
+        pieces = np.zeros(self.N * maxp * 2)
+        _check(self.L.st_partition_export(self.h, _ptr(I), _ptr(npc), _ptr(pieces), maxp), "st_partition_export")
+        pieces = pieces.reshape(self.N, maxp, 2)
+        return I.reshape(self.N, 2), [pieces[i, :npc[i]].copy() for i in range(self.N)]

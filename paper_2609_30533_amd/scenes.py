@@ -293,8 +293,8 @@ def synthetic_edges(prob: Problem, n_edges: int, seed: int, bridge_mix: bool = F
     """Speed-feasible synthetic edges.
 
     x_a ~ U(C x [0, H]); direction uniform on the unit sphere of C; length
-    D ~ U[0, eta] (or U[0, 4 eta] for the bridge mix); t_b = t_a + D / (v u)
-    with u ~ U[0.25, 1].  Returns (xa, xb) as FP32 arrays of shape (E, d+1),
+    D ~ U[0, eta] (or U[0, 4 eta] for the bridge mix), reflected at the box
+    faces; t_b = t_a + D / (v u) with u ~ U[0.25, 1], capped at H.  Returns (xa, xb) as FP32 arrays of shape (E, d+1),
     time last.
     """
     rng = np.random.default_rng([0xED9E, seed])
@@ -306,7 +306,11 @@ def synthetic_edges(prob: Problem, n_edges: int, seed: int, bridge_mix: bool = F
     dirs /= np.maximum(np.linalg.norm(dirs, axis=1, keepdims=True), 1e-12)
     scale = 4.0 if bridge_mix else 1.0
     length = rng.uniform(0.0, prob.params.eta * scale, size=n_edges)
-    qb = np.clip(qa + dirs * length[:, None], lo, hi)
+    qb = qa + dirs * length[:, None]
+    # reflect at the box faces (clipping would park endpoints exactly on them)
+    qb = np.where(qb > hi, 2 * hi - qb, qb)
+    qb = np.where(qb < lo, 2 * lo - qb, qb)
+    qb = np.clip(qb, lo, hi)
     u = rng.uniform(0.25, 1.0, size=n_edges)
     tb = np.minimum(ta + length / (prob.v_max * u), prob.t_max)
     xa = np.concatenate([qa, ta[:, None]], axis=1).astype(np.float32)

@@ -1,0 +1,239 @@
+"""Parity of the sampling, extend and planning entry points with the oracle.
+
+The extend batch is compared iteration by iteration on identical inputs: the
+device state is exported after every batch, rounded to FP32 and imported into
+the oracle (resynchronised lockstep), the device draws the samples and both
+sides run Alg. 1 on them.  Decisions must agree exactly except where the
+oracle flags a numerically fragile choice (near-tie or near speed cone,
+clearance within 1e-4); continuous results agree within a relative 1e-5.
+Every planned path is re-validated by the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2609_30533_amd import scenes
+from tests.gpu_util import banner, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+MARGIN = 1e-4
+
+
+def _small(prob, batch, cap_f=1 << 14, cap_b=1 << 11, groups=None):
+    prob.params.batch = batch
+    prob.params.cap_fwd = cap_f
+    prob.params.cap_bwd = cap_b
+    if groups:
+        prob.params.n_groups = groups
+    return prob
+
+
+def _to_np(s):
+    return {k: v.cpu().numpy() for k, v in s.items()}
+
+
+def _resync(gp, op, prob):
+    """Load the device state into the oracle planner."""
+    st = gp.export()
+    inf = gp.info()
+    slots = gp.slots() if prob.params.variant == 1 else None
+    op.import_state(st["counts"], st["x"].astype(np.float64), st["parent"], st["cost"].astype(np.float64),
+                    st["rootT"].astype(np.float64), inf["U"], inf["C"], inf["inc_fwd"], inf["inc_bwd"], inf["iter"],
+                    slots)
+    return st
+
+
+PROBS = [
+    ("disc2d-ir", lambda: _small(scenes.disc2d(1), 512)),
+    ("arm6-ir", lambda: _small(scenes.arm6(1), 1024, groups=8)),
+    ("disc2d-rr", lambda: _small(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 512)),
+    ("arm7-rr", lambda: _small(scenes.arm7rr(2, n_obs=16), 1024, groups=16)),
+]
+
+
+@pytest.mark.parametrize("name,make", PROBS, ids=[p[0] for p in PROBS])
+def test_sampling_matches_oracle(oracle_lib, name, make):
+    from paper_2609_30533_amd.lib import Problem
+    prob = make()
+    banner("sample %s" % name)
+    gp = Problem(prob)
+    op = oracle_lib.Planner(prob)
+    o = oracle_lib.Oracle(prob)
+    B = prob.params.batch
+    for it in (0, 1, 7):
+        s = _to_np(gp.sample(it))
+        r = op.sample(it, B)
+        assert np.array_equal(s["dir"], r["dir"])
+        assert np.array_equal(s["grp"], r["grp"])
+        np.testing.assert_allclose(s["qr"], r["qr"], rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(s["T"], r["T"], rtol=1e-6, atol=1e-6)
+        diff = np.where(s["flags"] != r["flags"])[0]
+        for i in diff:
+            # only fragile root checks or a near-empty Eq. 6 interval may differ
+            _, m = o.state_valid(np.r_[prob.q_goal, r["T"][i]])
+            q = r["qr"][:, i]
+            lo = np.linalg.norm(q - prob.q_start) / prob.v_max
+            hi = r["T"][i] - np.linalg.norm(q - prob.q_goal) / prob.v_max
+            assert abs(m) <= MARGIN or abs(hi - lo) <= 1e-5 * max(1.0, abs(hi)), (i, s["flags"][i], r["flags"][i])
+        assert len(diff) <= 0.01 * B
+        ok = (s["flags"] & 1) == 0
+        np.testing.assert_allclose(s["tr"][ok], r["tr"][ok], rtol=1e-5, atol=2e-5)
+
+
+def _compare_batch(prob, s, g, r):
+    """Compare one extend batch.  Returns (exempt workers, exempt workers whose
+    outcome differs); non-exempt workers must agree."""
+    B = len(s["dir"])
+    exempt = (r["amb"] != 0) | (r["edge_margin"] <= MARGIN) | (r["bridge_margin"] <= MARGIN)
+    skip = (s["flags"] & 1) != 0
+    n_ex = n_ex_diff = 0
+    pool_diverged = set()
+    for w in range(B):
+        if skip[w]:
+            assert g["status"][w] == 0 and r["status"][w] == 0
+            continue
+        pool = 0 if s["dir"][w] == 0 else 1 + s["grp"][w]
+        if exempt[w]:
+            n_ex += 1
+            ok_r = r["bridge_ok"][w] if (r["status"][w] == 2 and r["bridge"][w] >= 0) else 0
+            diff = (g["status"][w] != r["status"][w] or g["parent"][w] != r["parent"][w] or
+                    (r["status"][w] == 2 and (g["bridge"][w] != r["bridge"][w] or g["bridge_ok"][w] != ok_r)))
+            if diff:
+                n_ex_diff += 1
+                pool_diverged.add(pool)
+            continue
+        assert g["status"][w] == r["status"][w], (w, g["status"][w], r["status"][w])
+        if r["status"][w] < 2:
+            continue
+        assert g["parent"][w] == r["parent"][w], (w, g["parent"][w], r["parent"][w])
+        np.testing.assert_allclose(g["xnew"][:, w], r["xnew"][:, w], rtol=1e-5, atol=2e-5)
+        if pool not in pool_diverged:
+            assert g["new_idx"][w] == r["new_idx"][w], (w, g["new_idx"][w], r["new_idx"][w])
+        if r["status"][w] != 2:
+            continue
+        assert g["bridge"][w] == r["bridge"][w], (w, g["bridge"][w], r["bridge"][w])
+        ok_r = r["bridge_ok"][w] if r["bridge"][w] >= 0 else 0
+        assert g["bridge_ok"][w] == ok_r, (w, g["bridge_ok"][w], ok_r)
+        if ok_r:
+            assert abs(g["Up"][w] - r["Up"][w]) <= 1e-5 * max(1.0, r["Up"][w])
+            assert abs(g["Cp"][w] - r["Cp"][w]) <= 1e-5 * max(1.0, r["Cp"][w]) + 2e-5
+    return n_ex, n_ex_diff
+
+
+@pytest.mark.parametrize("name,make", PROBS, ids=[p[0] for p in PROBS])
+def test_extend_lockstep_resync(oracle_lib, name, make):
+    from paper_2609_30533_amd.lib import Problem
+    prob = make()
+    banner("extend %s" % name)
+    gp = Problem(prob)
+    op = oracle_lib.Planner(prob)
+    total_ex = total_diff = total = 0
+    for it in range(12):
+        _resync(gp, op, prob)
+        s_dev = gp.sample(it)
+        s = _to_np(s_dev)
+        g = _to_np(gp.extend(s_dev))
+        sr = dict(dir=s["dir"], flags=s["flags"], grp=s["grp"], T=s["T"].astype(np.float64),
+                  qr=s["qr"].astype(np.float64), tr=s["tr"].astype(np.float64))
+        r = op.extend(sr)
+        n_ex, n_diff = _compare_batch(prob, s, g, r)
+        total_ex += n_ex
+        total_diff += n_diff
+        total += int(((s["flags"] & 1) == 0).sum())
+        gi, oi = gp.info(), op.info()
+        if n_diff == 0:
+            # same decisions: same incumbent and the same pool sizes
+            if math.isfinite(oi["U"]):
+                assert abs(gi["U"] - oi["U"]) <= 1e-5 * max(1.0, oi["U"])
+                assert abs(gi["C"] - oi["C"]) <= 1e-5 * max(1.0, oi["C"]) + 2e-5
+            else:
+                assert not math.isfinite(gi["U"])
+            assert np.array_equal(gp.export()["counts"], op.counts())
+    banner("%s: %d workers, %d exempt, %d exempt with a different outcome" % (name, total, total_ex, total_diff))
+    assert total > 0
+    assert total_ex <= 0.5 * total
+    assert total_diff <= 0.02 * total, (total_diff, total)
+
+
+PLAN_CASES = [
+    # (name, problem, iterations, must solve)
+    ("disc2d-ir-0", lambda: _small(scenes.disc2d(0), 512), 60, True),
+    ("disc2d-ir-2", lambda: _small(scenes.disc2d(2), 512), 60, True),
+    ("disc2d-ir-3", lambda: _small(scenes.disc2d(3), 512), 60, True),
+    ("disc2d-rr-0", lambda: _small(scenes.disc2d(0, params=scenes.Params(variant=1, n_groups=8)), 512), 60, True),
+    ("disc2d-rr-2", lambda: _small(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 512), 60, True),
+    ("arm6-ir-2", lambda: _small(scenes.arm6(2), 1024, groups=8), 200, True),
+    ("arm7-rr-1", lambda: _small(scenes.arm7rr(1, n_obs=8), 1024, groups=16), 300, False),
+    ("arm7-rr-3", lambda: _small(scenes.arm7rr(3, n_obs=8), 1024, groups=16), 300, False),
+]
+
+
+@pytest.mark.parametrize("name,make,iters,must", PLAN_CASES, ids=[c[0] for c in PLAN_CASES])
+def test_plan_paths_validate(oracle_lib, name, make, iters, must):
+    from paper_2609_30533_amd.lib import Problem
+    prob = make()
+    banner("plan %s" % name)
+    o = oracle_lib.Oracle(prob)
+    gp = Problem(prob)
+    res = gp.plan(max_iters=iters, iters_per_sync=4)
+    inf = gp.info()
+    banner("%s: rc %d U %.4f C %.4f first iter %d first %.2f ms total %.2f ms iters %d" % (
+        name, res["rc"], res["U"], res["C"], res["first_iter"], res["first_ms"], res["total_ms"], res["iterations"]))
+    if must:
+        assert res["rc"] == 0
+    if res["rc"] == 0:
+        ok, msg = o.validate_path(res["states"], res["U"], res["C"], rel_tol=1e-4)
+        assert ok, msg
+        assert res["U"] >= inf["L"] - 1e-5
+        assert res["first_iter"] >= 0 and res["first_ms"] > 0
+
+
+def test_roots_update_after_improvement(oracle_lib):
+    """After a strict drop of U every active recycling root lies below U and
+    every recycled slot holds a valid root in [L_grid, U)."""
+    from paper_2609_30533_amd.lib import Problem
+    prob = _small(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 512)
+    gp = Problem(prob)
+    o = oracle_lib.Oracle(prob)
+    prev_gen = gp.slots()[2].copy()
+    for it in range(30):
+        gp.iterate(1)
+        inf = gp.info()
+        T, act, gen, k = gp.slots()
+        assert np.all(gen >= prev_gen)
+        if math.isfinite(inf["U"]):
+            assert np.all(T[act == 1] < inf["U"])
+            for sl in np.where(gen > prev_gen)[0]:
+                assert T[sl] < inf["U"] and o.state_valid(np.r_[prob.q_goal, T[sl]])[0]
+        prev_gen = gen.copy()
+
+
+def test_interval_root_partition_matches_oracle(oracle_lib):
+    from paper_2609_30533_amd.lib import Problem
+    prob = _small(scenes.arm6(3), 256)
+    gp = Problem(prob)
+    op = oracle_lib.Planner(prob)
+    I1, p1 = gp.partition()
+    I2, p2 = op.partition()
+    np.testing.assert_allclose(I1, I2, rtol=1e-12, atol=1e-12)
+    for a, b in zip(p1, p2):
+        assert a.shape == b.shape
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+def test_invalid_arguments_are_errors():
+    from paper_2609_30533_amd import lib
+    prob = scenes.disc2d(0)
+    prob.t_min = 11.0   # t_min > t_max
+    with pytest.raises(lib.StError):
+        lib.Problem(prob)
+    prob = scenes.disc2d(0)
+    prob.v_max = 0.0
+    with pytest.raises(lib.StError):
+        lib.Problem(prob)
+    prob = scenes.disc2d(0)
+    prob.q_start = np.array([2.0, 0.5])    # outside C
+    with pytest.raises(lib.StError):
+        lib.Problem(prob)
+    torch_cuda()
