@@ -65,6 +65,7 @@ extern "C" {
 /* sample flags (st_samples.flags) */
 #define ST_FLAG_SKIP 1       /* root or query sample rejected: the worker does nothing */
 #define ST_FLAG_USE_NEW 2    /* backward worker uses the virtual root (q_g, T) as its source */
+#define ST_FLAG_LEARNED 4    /* the sample came from the learned proposal */
 
 /* extend status (st_extend_out.status) */
 #define ST_STATUS_SKIPPED 0
@@ -269,6 +270,57 @@ int st_slots_export(st_problem *p, double *slot_T, int32_t *slot_active, uint32_
 int st_goal_grid_export(st_problem *p, uint8_t *free_out);
 /* interval-root allocation: I [N][2], n_pieces [N], pieces [N][maxp][2] */
 int st_partition_export(st_problem *p, double *I, int32_t *n_pieces, double *pieces, int32_t maxp);
+
+/* ---- learned proposal (an addition to the paper's method) ---------------- */
+
+/* The network proposes (q, t) query samples and goal arrival times; a worker
+ * uses it with probability `mix` and the plain sampler otherwise, so the plain
+ * sampler keeps full support.  Inputs per problem: core [16] = (q_s / pi,
+ * q_g / pi, each padded to 7; t_min / 60, t_max / 60) and obstacle rows
+ * [O][65] = 16 waypoints (t / 60, x, y, z; the last waypoint repeated) and the
+ * radius, with a mask [O].  Output z [168] per problem: 8 mixture logits,
+ * 8 x 8 means, 8 x 8 log standard deviations of the normalised state
+ * (q / pi in slots 0..d-1, t / 60 in slot 7), 32 arrival-histogram logits over
+ * [t_min, t_max].  Weights are a flat FP32 vector (We[65][64], be, W1[96][256],
+ * b1, W2..W4 [256][256], b2..b4, W5[256][168], b5); GEMMs run on bfloat16
+ * matrix cores with FP32 accumulation. */
+#define ST_MLP_OUTPUTS 168
+typedef struct st_mlp st_mlp;
+/* Device buffers for batches of up to max_batch problems / examples. */
+int st_mlp_create(int32_t max_batch, int32_t max_obstacles, st_mlp **out);
+void st_mlp_destroy(st_mlp *net);
+int64_t st_mlp_param_count(void);
+/* host_in (may be NULL): new FP32 weights (Adam state reset); host_out (may be
+ * NULL): receives the weights.  Synchronous. */
+int st_mlp_params(st_mlp *net, const float *host_in, float *host_out);
+/* Gradients of the last st_mlp_backward (host, param_count floats).  Synchronous. */
+int st_mlp_grads(st_mlp *net, float *host_out);
+/* Forward pass for M rows: core [M][16], obs [M][O][65], mask [M][O] (device);
+ * z_out [M][168] (device, may be NULL).  Async on stream. */
+int st_mlp_forward(st_mlp *net, int32_t M, int32_t O, const float *core, const float *obs, const float *mask,
+                   float *z_out, void *stream);
+/* Loss of the last forward pass: mixture negative log-likelihood of K path
+ * states y [M][K][8] (mask ymask [M][K], dimension mask dmask [M][8]) plus the
+ * cross-entropy of the arrival bin ubin [M]; loss_per_out [M] (device, may be
+ * NULL); keeps dL/dz for st_mlp_backward (the loss is the mean over rows). */
+int st_mlp_loss(st_mlp *net, int32_t K, const float *y, const float *ymask, const float *dmask, const int32_t *ubin,
+                float *loss_per_out, void *stream);
+int st_mlp_backward(st_mlp *net, void *stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 weights. */
+int st_mlp_adam(st_mlp *net, float lr, void *stream);
+/* Install a problem's network output z (device [168]; NULL clears) and the
+ * probability `mix` that a worker draws from it.  Async on stream. */
+int st_proposal_set(st_problem *p, const float *z, float mix, void *stream);
+
+/* ---- tuning ---------------------------------------------------------------- */
+
+/* Launch shapes of the collision kernels: obstacles held in registers per
+ * tile (4, 8 or 16, dividing the padded obstacle count; 0 keeps the current
+ * value) and lanes per edge chunk for extension edges, bridge edges and
+ * st_check_edges (powers of two up to 64; 0 keeps).  Results do not depend
+ * on these.  Synchronous; drops captured iteration graphs. */
+int st_set_tuning(st_problem *p, int32_t obstacle_tile, int32_t lanes_extension, int32_t lanes_bridge,
+                  int32_t lanes_check);
 
 /* ---- measurement ---------------------------------------------------------- */
 

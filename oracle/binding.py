@@ -131,6 +131,7 @@ def _declare(L):
     L.orc_planner_export.argtypes = [C.c_void_p, f64, i32, f64, f64]
     L.orc_planner_import.argtypes = [C.c_void_p, i64, f64, i32, f64, f64, C.c_double, C.c_double, C.c_int64,
                                      C.c_int64, C.c_int64, _opt(f64), _opt(i32), _opt(u32), _opt(i64)]
+    L.orc_planner_set_proposal.argtypes = [C.c_void_p, _opt(f64), C.c_double]
     L.orc_validate_path.argtypes = [S, C.c_int64, f64, C.c_double, C.c_double, C.c_double, C.c_char_p, C.c_int]
     L.orc_validate_path.restype = C.c_int
 
@@ -357,6 +358,10 @@ class Planner:
         o["xnew"] = o["xnew"].reshape(d + 1, B)
         o["improved"] = r
         return o
+
+    def set_proposal(self, z, mix):
+        self.lib.orc_planner_set_proposal(self.h, None if z is None else np.ascontiguousarray(z, dtype=np.float64),
+                                          float(mix))
 
     def run(self, iters):
         return self.lib.orc_planner_run(self.h, int(iters))

@@ -185,27 +185,3 @@ def adam_step(p, g, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         vh = v[k] / (1 - b2 ** t)
         p[k] = (p[k] - lr * mh / (np.sqrt(vh) + eps)).astype(np.float32)
     return p, m, v
-
-
-# ----------------------------------------------------------------------------
-# feature rows from a problem (data preparation shared by training and tests)
-# ----------------------------------------------------------------------------
-
-def problem_features(prob, o_max=32):
-    """core [16], obs [o_max, 65], mask [o_max] for one generated problem."""
-    core = np.zeros(CORE)
-    core[:prob.d] = prob.q_start / Q_SCALE
-    core[7:7 + prob.d] = prob.q_goal / Q_SCALE
-    core[14] = prob.t_min / T_SCALE
-    core[15] = prob.t_max / T_SCALE
-    obs = np.zeros((o_max, ENC_IN))
-    mask = np.zeros(o_max)
-    for o in range(min(prob.n_obs, o_max)):
-        n = int(prob.n_wp[o])
-        for k in range(16):
-            w = prob.wp[o, min(k, n - 1)]
-            obs[o, 4 * k] = w[0] / T_SCALE
-            obs[o, 4 * k + 1:4 * k + 4] = w[1:4]
-        obs[o, 64] = prob.obs_r[o]
-        mask[o] = 1.0
-    return core, obs, mask

@@ -18,6 +18,7 @@
 #include <string.h>
 
 #define INF (1.0 / 0.0)
+#define PI 3.14159265358979323846
 
 /* ========================================================================= */
 /* Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw,  */
@@ -59,11 +60,12 @@ static double unit24(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0);
 /* Uniform index in {0..n-1} from a draw, in integer arithmetic. */
 static int32_t index24(uint32_t x, int32_t n) { return (int32_t)(((uint64_t)(x >> 8) * (uint64_t)n) >> 24); }
 
-/* The 16 draws of one worker in one iteration: four Philox blocks keyed by
- * (seed, problem) with counter (iteration, worker, block, 0). */
-static void worker_draws(const orc_scene *sc, int64_t iter, int64_t w, uint32_t u[16]) {
+/* The draws of one worker in one iteration: Philox blocks keyed by (seed,
+ * problem) with counter (iteration, worker, block, 0); four blocks for the
+ * plain sampler, seven with the learned proposal. */
+static void worker_draws(const orc_scene *sc, int64_t iter, int64_t w, uint32_t u[28], int nblk) {
     uint32_t key[2] = {sc->seed, sc->problem_id};
-    for (uint32_t b = 0; b < 4; ++b) {
+    for (uint32_t b = 0; b < (uint32_t)nblk; ++b) {
         uint32_t ctr[4] = {(uint32_t)iter, (uint32_t)w, b, 0u};
         orc_philox4x32_10(ctr, key, u + 4 * b);
     }
@@ -499,7 +501,41 @@ struct orc_planner {
     int64_t iter;
     int32_t overflow;
     int64_t n_edge_checks, n_bridge_checks; /* edges decided (for throughput) */
+    /* learned proposal (an addition to the paper's method) */
+    double prop_mix, prop_wcum[8], prop_mu[64], prop_sd[64], prop_hcum[32];
 };
+
+/* Install the proposal network's output z[168] (8 mixture logits, 8x8 means,
+ * 8x8 log standard deviations of the normalised state q/pi, t/60; 32
+ * arrival-histogram logits over [t_min, t_max]) and the probability mix of a
+ * learned draw.  z = NULL or mix = 0 switches the proposal off. */
+void orc_planner_set_proposal(orc_planner *p, const double *z, double mix) {
+    p->prop_mix = 0.0;
+    if (!z || !(mix > 0.0)) return;
+    double mx = -INF, s = 0.0, acc = 0.0;
+    for (int c = 0; c < 8; ++c) mx = fmax(mx, z[c]);
+    for (int c = 0; c < 8; ++c) s += exp(z[c] - mx);
+    for (int c = 0; c < 8; ++c) {
+        acc += exp(z[c] - mx) / s;
+        p->prop_wcum[c] = acc;
+    }
+    p->prop_wcum[7] = 1.0;
+    for (int i = 0; i < 64; ++i) {
+        p->prop_mu[i] = z[8 + i];
+        p->prop_sd[i] = exp(z[72 + i]);
+    }
+    mx = -INF;
+    s = 0.0;
+    acc = 0.0;
+    for (int b = 0; b < 32; ++b) mx = fmax(mx, z[136 + b]);
+    for (int b = 0; b < 32; ++b) s += exp(z[136 + b] - mx);
+    for (int b = 0; b < 32; ++b) {
+        acc += exp(z[136 + b] - mx) / s;
+        p->prop_hcum[b] = acc;
+    }
+    p->prop_hcum[31] = 1.0;
+    p->prop_mix = mix;
+}
 
 static int64_t push_node(orc_planner *p, int pool, const double *x, int32_t parent, double cost, double rootT) {
     if (p->count[pool] >= p->cap[pool]) { p->overflow = 1; return -1; }
@@ -659,7 +695,9 @@ static int ir_group_active(const orc_planner *p, int g) {
 /* ========================================================================= */
 /* Sampling (Sec. IV-B with Eq. 6 for interval root; Alg. 3 for recycling). */
 /* Draws: u[0] group, u[1] guided-vs-uniform, u[2] piece, u[3] position,     */
-/* u[4..10] q_r, u[11] t_r, u[12] p_new.                                     */
+/* u[4..10] q_r, u[11] t_r, u[12] p_new; learned proposal: u[13] learned or  */
+/* plain, u[14] component, u[15] histogram bin, u[16..23] Box-Muller pairs,  */
+/* u[24] position inside the bin.                                            */
 /* Reading: direction alternates as (worker + iteration) mod 2, 0 = forward. */
 /* ========================================================================= */
 
@@ -673,18 +711,66 @@ void orc_planner_sample(orc_planner *p, int64_t iter, int64_t B, int8_t *dir, ui
     if (sc->variant == ORC_IR)
         for (int g = 0; g < N; ++g) gact[g] = (uint8_t)ir_group_active(p, g);
     for (int64_t w = 0; w < B; ++w) {
-        uint32_t u[16];
-        worker_draws(sc, iter, w, u);
+        uint32_t u[28];
+        const int learned = p->prop_mix > 0.0;
+        worker_draws(sc, iter, w, u, learned ? 7 : 4);
         int8_t dr = (int8_t)((w + iter) & 1);
         uint8_t fl = 0;
         int32_t g = 0;
         double Tw = 0.0, trw = 0.0;
         double q[ORC_MAX_DOF];
         for (int j = 0; j < d; ++j) q[j] = sc->q_lo[j] + unit24(u[4 + j]) * (sc->q_hi[j] - sc->q_lo[j]);
+        /* learned draw: (q, t) from the mixture component chosen by u[14],
+         * Gaussian variates by the Box-Muller transform */
+        const int use_net = learned && unit24(u[13]) < p->prop_mix;
+        double ylearn_t = 0.0;
+        if (use_net) {
+            fl |= ORC_LEARNED;
+            int c = 0;
+            while (c < 7 && !(unit24(u[14]) < p->prop_wcum[c])) ++c;
+            double nrm[8];
+            for (int k = 0; k < 4; ++k) {
+                double r = sqrt(-2.0 * log(1.0 - unit24(u[16 + 2 * k])));
+                double th = 2.0 * PI * unit24(u[17 + 2 * k]);
+                nrm[2 * k] = r * cos(th);
+                nrm[2 * k + 1] = r * sin(th);
+            }
+            int inside = 1;
+            for (int j = 0; j < d; ++j) {
+                q[j] = PI * (p->prop_mu[c * 8 + j] + p->prop_sd[c * 8 + j] * nrm[j]);
+                if (q[j] < sc->q_lo[j] || q[j] > sc->q_hi[j]) inside = 0;
+            }
+            ylearn_t = 60.0 * (p->prop_mu[c * 8 + 7] + p->prop_sd[c * 8 + 7] * nrm[7]);
+            if (!inside) fl |= ORC_SKIP;
+        }
         if (sc->variant == ORC_IR) {
             g = index24(u[0], N);
             if (!(p->L < Ubar)) {
                 fl |= ORC_SKIP;
+            } else if (use_net) {
+                /* T from the arrival histogram over [t_min, t_max]; the group is
+                 * the one whose uniform interval holds T */
+                int b = 0;
+                while (b < 31 && !(unit24(u[15]) < p->prop_hcum[b])) ++b;
+                double wb = (sc->t_max - sc->t_min) / 32.0;
+                Tw = sc->t_min + ((double)b + unit24(u[24])) * wb;
+                if (!(Tw >= p->L && Tw < Ubar)) {
+                    fl |= ORC_SKIP;
+                } else {
+                    int gi = (int)floor((Tw - p->L) / ((Ubar - p->L) / N));
+                    g = gi < 0 ? 0 : (gi >= N ? N - 1 : gi);
+                    if (!(fl & ORC_SKIP)) {
+                        double xg[ORC_MAX_DOF + 1];
+                        for (int j = 0; j < d; ++j) xg[j] = sc->q_g[j];
+                        xg[d] = Tw;
+                        if (!orc_state_valid(sc, xg, NULL)) fl |= ORC_SKIP;
+                        double lo = config_dist(d, sc->q_s, q) / v;
+                        double hi = Tw - config_dist(d, q, sc->q_g) / v;
+                        trw = ylearn_t;
+                        if (hi < lo || !(trw >= lo && trw <= hi)) fl |= ORC_SKIP;
+                        if (dr == 1 && (!gact[g] || unit24(u[12]) <= sc->p_new)) fl |= ORC_USE_NEW;
+                    }
+                }
             } else {
                 if (unit24(u[1]) < sc->p_guided && p->np[g] > 0) {
                     /* pick a guided portion with probability proportional to its length */

@@ -36,7 +36,7 @@ enum { ORC_IR = 0, ORC_RR = 1 };
 enum { ORC_METRIC_RHO = 0, ORC_METRIC_CONFIG = 1 };
 
 /* sample flags */
-enum { ORC_SKIP = 1, ORC_USE_NEW = 2 };
+enum { ORC_SKIP = 1, ORC_USE_NEW = 2, ORC_LEARNED = 4 };
 /* extend status */
 enum { ORC_ST_SKIPPED = 0, ORC_ST_TRAPPED = 1, ORC_ST_ADVANCED = 2, ORC_ST_DROPPED = 3 };
 

@@ -38,8 +38,7 @@ static bool finite(double x) { return std::isfinite(x); }
 static int ot_of(int O) {
     if (O <= 4) return 4;
     if (O <= 8) return 8;
-    if (O <= 16) return 16;
-    return 32;
+    return 16;
 }
 
 template <class T>
@@ -126,6 +125,7 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.O = O;
     const int OT = ot_of(O);
     sc.O_pad = std::max(OT, (O + OT - 1) / OT * OT);
+    sc.ot = OT;
     sc.v = (float)D->v_max;
     sc.H = (float)D->t_max;
     sc.h = (float)D->params.h;
@@ -229,7 +229,11 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
         }
     }
     if (shared && O == 0) segt.assign(nseg + 1, INFINITY);
-    sc.lds_f4 = sc.O_pad * nseg * 2 + (shared ? 0 : (int)((segt.size() + 3) / 4));
+    // LDS: segment table, spheres, pair table (padded to float4), times
+    sc.lds_sph = sc.O_pad * nseg * 2;
+    sc.lds_r2 = sc.lds_sph + S;
+    sc.lds_t = sc.lds_r2 + (S * sc.O_pad + 3) / 4;
+    sc.lds_f4 = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));
     int rc;
     if ((rc = dev_upload(&p->d_sph, sph.data(), sph.size())) != ST_OK) return rc;
     if ((rc = dev_upload(&p->d_R2, R2.data(), R2.size())) != ST_OK) return rc;
@@ -407,7 +411,11 @@ static int init_state(st_problem *p) {
 
 static void destroy(st_problem *p) {
     if (!p) return;
+    graphs_free(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
     work_free(p);
+    edge_bufs_free(p->ebufs);
+    edge_bufs_free(p->ebufs_api);
     for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
     void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
                     p->tree.x, p->tree.parent, p->tree.cost, p->tree.rootT, p->d_plan};
@@ -451,6 +459,15 @@ int st_problem_create(const st_problem_desc *D, st_problem **out) {
     for (int j = 0; j < p->d; ++j) D2 += (p->q_g[j] - p->q_s[j]) * (p->q_g[j] - p->q_s[j]);
     p->Lg = sqrt(D2) / p->v_max;
     p->L = std::max(p->Lg, p->t_min);
+    // default lanes per edge chunk: enough for a typical steered edge
+    {
+        const double n_typ = p->prm.eta / p->prm.h + 1.0;
+        int shift = 3;
+        while ((1 << shift) < n_typ && shift < 6) ++shift;
+        p->tune_ext = shift;
+        p->tune_api = shift;
+        p->tune_br = 6;
+    }
     if ((rc = build_scene(p, D)) != ST_OK || (rc = build_goal_grid(p)) != ST_OK || (rc = alloc_trees(p)) != ST_OK ||
         (rc = init_state(p)) != ST_OK || (rc = work_reserve(p, p->prm.batch)) != ST_OK) {
         destroy(p);
@@ -473,6 +490,33 @@ int st_problem_reset(st_problem *p) {
     return init_state(p);
 }
 
+int st_set_tuning(st_problem *p, int32_t obstacle_tile, int32_t lanes_extension, int32_t lanes_bridge,
+                  int32_t lanes_check) {
+    if (!p) return fail(ST_EINVAL, "null problem");
+    auto shift_of = [](int32_t lanes, int32_t *out) {
+        for (int s = 0; s <= 6; ++s)
+            if ((1 << s) == lanes) {
+                *out = s;
+                return true;
+            }
+        return lanes == 0;
+    };
+    int32_t se = p->tune_ext, sb = p->tune_br, sk = p->tune_api;
+    if (!shift_of(lanes_extension, &se) || !shift_of(lanes_bridge, &sb) || !shift_of(lanes_check, &sk))
+        return fail(ST_EINVAL, "lanes must be 0 (keep) or a power of two up to 64");
+    if (obstacle_tile != 0) {
+        if ((obstacle_tile != 4 && obstacle_tile != 8 && obstacle_tile != 16) || p->sc.O_pad % obstacle_tile)
+            return fail(ST_EINVAL, "obstacle tile must be 4, 8 or 16 and divide %d", p->sc.O_pad);
+        p->sc.ot = obstacle_tile;
+    }
+    p->tune_ext = se;
+    p->tune_br = sb;
+    p->tune_api = sk;
+    ST_HIP(hipDeviceSynchronize());
+    graphs_free(p);
+    return ST_OK;
+}
+
 int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out, void *stream) {
     if (!p || M < 0 || (M > 0 && (!x || !free_out))) return fail(ST_EINVAL, "st_check_states: bad arguments");
     ST_HIP(launch_check_states(p->sc, M, x, free_out, (hipStream_t)stream));
@@ -482,11 +526,12 @@ int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out,
 int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
                    int32_t *first_hit, void *stream) {
     if (!p || E < 0 || (E > 0 && (!xa || !xb || !free_out))) return fail(ST_EINVAL, "st_check_edges: bad arguments");
-    // lanes per edge: enough for a typical steered edge of the problem
-    const double n_typ = std::max(p->prm.eta, p->prm.eta) / p->prm.h + 1.0;
-    int shift = 4;
-    while ((1 << shift) < n_typ && shift < 6) ++shift;
-    ST_HIP(launch_check_edges(p->sc, E, xa, xb, nullptr, free_out, first_hit, shift, (hipStream_t)stream));
+    if (E == 0) return ST_OK;
+    // separate from the planner's buffers, which captured graphs refer to
+    int rc = edge_bufs_reserve(p->ebufs_api, E);
+    if (rc != ST_OK) return rc;
+    ST_HIP(launch_check_edges(p->sc, p->ebufs_api, E, xa, xb, nullptr, free_out, first_hit, p->tune_api,
+                              (hipStream_t)stream));
     return ST_OK;
 }
 

@@ -29,7 +29,7 @@
 
 namespace st {
 
-constexpr int kScanThreads = 64;
+constexpr int kTileQ = 256;  // queries per scan tile (one per thread)
 constexpr int kMaxNch = 64;
 constexpr unsigned long long kNoKey = ~0ull;
 constexpr int kSetAllBackward = -2;
@@ -52,6 +52,7 @@ struct SampleArgs {
     float p_guided, p_new;
     uint32_t seed, pid;
     int64_t iter, B;
+    double t_min, t_max;  // arrival range (the learned histogram spans it)
     st_samples out;
 };
 
@@ -92,14 +93,19 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool act = w < a.B;
     const PlanDev *pl = a.pl;
-    uint32_t u[16];
+    // a negative iteration means "the planner's own counter" (graph replays)
+    const int64_t iter = a.iter >= 0 ? a.iter : (int64_t)pl->iter;
+    uint32_t u[28];
+    const bool learned = pl->prop_mix > 0.f;
+    const int nblk = learned ? 7 : 4;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const U4 r = philox4x32_10((uint32_t)a.iter, (uint32_t)w, (uint32_t)b, 0u, a.seed, a.pid);
+    for (int b = 0; b < 7; ++b) {
+        if (b >= nblk) break;
+        const U4 r = philox4x32_10((uint32_t)iter, (uint32_t)w, (uint32_t)b, 0u, a.seed, a.pid);
 #pragma unroll
         for (int k = 0; k < 4; ++k) u[4 * b + k] = r.x[k];
     }
-    const int8_t dir = (int8_t)((w + a.iter) & 1);
+    const int8_t dir = (int8_t)((w + iter) & 1);
     uint8_t flags = 0;
     int32_t g = 0;
     float T = 0.f, tr = 0.f;
@@ -108,10 +114,53 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
     for (int j = 0; j < kMaxDof; ++j)
         q[j] = j < sc.d ? sc.q_lo[j] + unit24f(u[4 + j]) * (sc.q_hi[j] - sc.q_lo[j]) : 0.f;
     bool check_root = false;
+    // learned draw: (q, t) from the mixture, T from the arrival histogram
+    const bool use_net = learned && unit24f(u[13]) < pl->prop_mix;
+    float y7 = 0.f;
+    if (use_net) {
+        flags |= ST_FLAG_LEARNED;
+        int c = 0;
+        while (c < 7 && !(unit24f(u[14]) < pl->prop_wcum[c])) ++c;
+        float nrm[8];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            // Box-Muller (Box and Muller, 1958) from two uniforms in (0, 1] and [0, 1)
+            const float r = sqrtf(-2.f * __logf(1.f - unit24f(u[16 + 2 * k])));
+            float sn, cs;
+            __sincosf(6.28318530717958648f * unit24f(u[17 + 2 * k]), &sn, &cs);
+            nrm[2 * k] = r * cs;
+            nrm[2 * k + 1] = r * sn;
+        }
+        bool inside = true;
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) {
+            if (j < sc.d) {
+                q[j] = 3.14159265358979324f * fmaf(pl->prop_sd[c * 8 + j], nrm[j], pl->prop_mu[c * 8 + j]);
+                inside = inside && q[j] >= sc.q_lo[j] && q[j] <= sc.q_hi[j];
+            }
+        }
+        y7 = 60.f * fmaf(pl->prop_sd[c * 8 + 7], nrm[7], pl->prop_mu[c * 8 + 7]);
+        if (!inside) flags |= ST_FLAG_SKIP;
+    }
     if (ir) {
         g = index24(u[0], a.N);
         if (!act || pl->done) {
             flags |= ST_FLAG_SKIP;
+        } else if (use_net) {
+            int b = 0;
+            while (b < 31 && !(unit24f(u[15]) < pl->prop_hcum[b])) ++b;
+            const double w = (a.t_max - a.t_min) / 32.0;
+            const double Td = a.t_min + ((double)b + unit24d(u[24])) * w;
+            const double L = a.win.L, Ubar = pl->Ubar;
+            if (!(Td >= L && Td < Ubar)) {
+                flags |= ST_FLAG_SKIP;
+            } else {
+                // the group whose uniform interval holds T
+                const int gi = (int)floor((Td - L) / ((Ubar - L) / a.N));
+                g = gi < 0 ? 0 : (gi >= a.N ? a.N - 1 : gi);
+                T = (float)Td;
+                check_root = !(flags & ST_FLAG_SKIP);
+            }
         } else {
             T = (float)ir_root_time(a.win, pl, g, u, a.p_guided);
             check_root = true;
@@ -128,7 +177,10 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
     }
     if (ir) {
         // the proposed root (q_g, T) is checked at its own time
-        const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, sc.q_g, T, check_root, 1ull << lane, 0ull);
+        float qg[kMaxDof];
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) qg[j] = sc.q_g[j];
+        const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, qg, T, check_root, 1ull << lane, 0ull);
         if (check_root) {
             if (hit) flags |= ST_FLAG_SKIP;
             // Eq. 6: t_r ~ U[D(q_s, q_r)/v, T - D(q_r, q_g)/v], empty interval rejected
@@ -143,7 +195,13 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
             }
             const float lo = sqrtf(ds) / sc.v, hi = T - sqrtf(dg) / sc.v;
             if (hi < lo) flags |= ST_FLAG_SKIP;
-            else tr = lo + unit24f(u[11]) * (hi - lo);
+            else if (use_net) {
+                // the learned time must satisfy the same bounds
+                tr = y7;
+                if (!(tr >= lo && tr <= hi)) flags |= ST_FLAG_SKIP;
+            } else {
+                tr = lo + unit24f(u[11]) * (hi - lo);
+            }
             if (dir == 1 && (!(pl->minRootT[g] < pl->U) || unit24f(u[12]) <= a.p_new)) flags |= ST_FLAG_USE_NEW;
         }
     }
@@ -175,6 +233,26 @@ struct PrepArgs {
     int32_t mode;       // 0 nearest node, 1 bridges
 };
 
+// Adds `amount` lanes' worth to bucket[set] with one atomic per distinct set
+// in the wave; returns each lane's position among the lanes of its set (in
+// lane order) plus the bucket's previous value.  Every lane must call it.
+__device__ __forceinline__ int wave_bucket_add(int *bucket, int set) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(set >= 0);
+    int pos = -1;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int ls = __shfl(set, leader, 64);
+        const uint64_t same = __ballot(set == ls) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bucket[ls], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if (set == ls) pos = base + __popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    return pos;
+}
+
 __global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
     __shared__ int cnt[kMaxPools + 2], cur[kMaxPools + 2];
     const int tid = threadIdx.x;
@@ -187,35 +265,38 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
         a.pl->improved = 0;
     }
     __syncthreads();
-    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+    for (int64_t base = 0; base < a.B; base += blockDim.x) {
+        const int64_t w = base + tid;
         int set = -1;
-        if (a.mode == 0) {
-            const uint8_t f = a.s.flags[w];
-            const int8_t dir = a.s.dir[w];
-            const int32_t g = a.s.grp[w];
-            if (!(f & ST_FLAG_SKIP)) {
-                if (dir == 0) set = 0;
-                else if (g >= 0 && g < a.n_pools - 1 &&
-                         !(a.variant == ST_INTERVAL_ROOT && (f & ST_FLAG_USE_NEW)))
-                    set = 1 + g;
+        if (w < a.B) {
+            if (a.mode == 0) {
+                const uint8_t f = a.s.flags[w];
+                const int8_t dir = a.s.dir[w];
+                const int32_t g = a.s.grp[w];
+                if (!(f & ST_FLAG_SKIP)) {
+                    if (dir == 0) set = 0;
+                    else if (g >= 0 && g < a.n_pools - 1 &&
+                             !(a.variant == ST_INTERVAL_ROOT && (f & ST_FLAG_USE_NEW)))
+                        set = 1 + g;
+                }
+                for (int j = 0; j < a.d; ++j) a.qbuf[w * (a.d + 1) + j] = a.s.qr[(int64_t)j * a.B + w];
+                a.qbuf[w * (a.d + 1) + a.d] = a.s.tr[w];
+                a.keys[w] = kNoKey;
+            } else {
+                // forward new nodes bridge into the backward forest (set 0), backward
+                // new nodes into the forward tree (set 1)
+                if (a.status[w] == ST_STATUS_ADVANCED) set = a.dir[w] == 0 ? 0 : 1;
             }
-            for (int j = 0; j < a.d; ++j) a.qbuf[w * (a.d + 1) + j] = a.s.qr[(int64_t)j * a.B + w];
-            a.qbuf[w * (a.d + 1) + a.d] = a.s.tr[w];
-            a.keys[w] = kNoKey;
-        } else {
-            // forward new nodes bridge into the backward forest (set 0), backward
-            // new nodes into the forward tree (set 1)
-            if (a.status[w] == ST_STATUS_ADVANCED) set = a.dir[w] == 0 ? 0 : 1;
+            a.set_of[w] = set;
         }
-        a.set_of[w] = set;
-        if (set >= 0) atomicAdd(&cnt[set], 1);
+        wave_bucket_add(cnt, set);
     }
     __syncthreads();
     if (tid == 0) {
         int off = 0, t = 0;
         for (int s = 0; s < nsets; ++s) {
             cur[s] = off;
-            for (int k = 0; k < cnt[s]; k += kScanThreads) {
+            for (int k = 0; k < cnt[s]; k += kTileQ) {
                 int set_id, sigma;
                 if (a.mode == 0) {
                     set_id = s;
@@ -226,16 +307,18 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
                     set_id = s == 0 ? kSetAllBackward : 0;
                     sigma = s == 0 ? -1 : 1;
                 }
-                a.tiles[t++] = make_int4(set_id, off + k, min(kScanThreads, cnt[s] - k), sigma);
+                a.tiles[t++] = make_int4(set_id, off + k, min(kTileQ, cnt[s] - k), sigma);
             }
             off += cnt[s];
         }
         a.n_tiles[0] = t;
     }
     __syncthreads();
-    for (int64_t w = tid; w < a.B; w += blockDim.x) {
-        const int set = a.set_of[w];
-        if (set >= 0) a.order[atomicAdd(&cur[set], 1)] = (int32_t)w;
+    for (int64_t base = 0; base < a.B; base += blockDim.x) {
+        const int64_t w = base + tid;
+        const int set = w < a.B ? a.set_of[w] : -1;
+        const int pos = wave_bucket_add(cur, set);
+        if (set >= 0) a.order[pos] = (int32_t)w;
     }
 }
 
@@ -261,92 +344,130 @@ struct ScanArgs {
     int32_t nch;
 };
 
+// One block = one tile of up to 256 queries (one per thread) against the
+// y-th of nch slices of its node set.  The set is a single pool or the
+// concatenation of the backward pools; nodes stream through LDS in rounds of
+// 256 (each thread loads one node, coalesced per SoA row), and the next
+// round is fetched into registers while the current one is scanned.
 template <int MODE>
-__global__ __launch_bounds__(kScanThreads) void k_scan(ScanArgs a) {
-    __shared__ float sx[kScanThreads][8];
-    __shared__ float sT[kScanThreads];
+__global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a) {
+    __shared__ float sx[kTileQ][8];
+    __shared__ float sT[kTileQ];
+    __shared__ int32_t sI[kTileQ];
+    __shared__ int32_t s_pool[kMaxPools + 1], s_pre[kMaxPools + 1];
+    __shared__ int32_t s_np;
     const int t = blockIdx.x;
     if (t >= a.n_tiles[0]) return;
-    const int lane = threadIdx.x;
+    const int tid = threadIdx.x;
     const int4 tile = a.tiles[t];
     const int set = tile.x, n = tile.z;
     const float sv = (float)tile.w * a.v;  // sigma * v
     const int d = a.tree.d;
-    const bool act = lane < n;
-    const int q = act ? (a.order ? a.order[tile.y + lane] : tile.y + lane) : 0;
+    const PlanDev *pl = a.pl;
+    const float U = a.use_snap ? pl->U_snap : pl->U;
+    if (tid == 0) {
+        // pools of the set and their prefix sums
+        int k = 0, acc = 0;
+        const int p_lo = set >= 0 ? set : 1, p_hi = set >= 0 ? set + 1 : a.tree.n_pools;
+        for (int p = p_lo; p < p_hi; ++p) {
+            if (a.variant == ST_ROOT_RECYCLING && set < 0 && !pl->slot_active[p - 1]) continue;
+            const int c = a.use_snap ? pl->count_snap[p] : pl->count[p];
+            if (c <= 0) continue;
+            s_pool[k] = p;
+            s_pre[k] = acc;
+            acc += c;
+            ++k;
+        }
+        s_pre[k] = acc;
+        s_np = k;
+    }
+    __syncthreads();
+    const int np = s_np;
+    const int64_t total = s_pre[np];
+    const int64_t c0 = (int64_t)blockIdx.y * total / a.nch, c1 = (int64_t)(blockIdx.y + 1) * total / a.nch;
+    const bool act = tid < n;
+    const int q = act ? (a.order ? a.order[tile.y + tid] : tile.y + tid) : 0;
     float qx[kMaxDof];
     float aq = 0.f;
 #pragma unroll
     for (int j = 0; j < kMaxDof; ++j) qx[j] = (act && j < d) ? a.qbuf[(int64_t)q * (d + 1) + j] : 0.f;
     if (act) aq = sv * a.qbuf[(int64_t)q * (d + 1) + d];
-    const PlanDev *pl = a.pl;
-    const float U = a.use_snap ? pl->U_snap : pl->U;
-    const int y = blockIdx.y;
     float best = INFINITY, bestT = INFINITY;
     int32_t bi = -1;
-    const int p_lo = set >= 0 ? set : 1, p_hi = set >= 0 ? set + 1 : a.tree.n_pools;
     const float *X = a.tree.x;
-    const int64_t total = a.tree.total;
-    for (int p = p_lo; p < p_hi; ++p) {
-        if (a.variant == ST_ROOT_RECYCLING && set < 0 && !pl->slot_active[p - 1]) continue;
-        const int64_t cnt = a.use_snap ? pl->count_snap[p] : pl->count[p];
-        const int64_t c0 = (int64_t)y * cnt / a.nch, c1 = (int64_t)(y + 1) * cnt / a.nch;
-        const int64_t base = pool_base(a.tree, p);
-        const bool filt = a.variant == ST_INTERVAL_ROOT && p > 0;
-        for (int64_t c = c0; c < c1; c += kScanThreads) {
-            const int64_t i = c + lane;
-            const bool ok = i < c1;
-            const int64_t gi = base + i;
+    const int64_t total_cap = a.tree.total;
+    const float nanf_ = __int_as_float(0x7fc00000);
+    // register stage for one node
+    float rx[8];
+    float rT = 0.f;
+    int32_t rI = -1;
+    auto fetch = [&](int64_t vbase) {
+        const int64_t v = vbase + tid;
+        rI = -1;
+        if (v < c1) {
+            int k = 0;
+            while (k + 1 < np && v >= s_pre[k + 1]) ++k;
+            const int p = s_pool[k];
+            const int64_t gi = pool_base(a.tree, p) + (v - s_pre[k]);
 #pragma unroll
             for (int j = 0; j < kMaxDof; ++j)
-                if (j < d) sx[lane][j] = ok ? X[(int64_t)j * total + gi] : 0.f;
-            float tn = ok ? X[(int64_t)d * total + gi] : 0.f;
-            float rt = (ok && (filt || MODE == kScanBridge)) ? a.tree.rootT[gi] : 0.f;
+                if (j < d) rx[j] = X[(int64_t)j * total_cap + gi];
+            float tn = X[(int64_t)d * total_cap + gi];
+            const bool filt = a.variant == ST_INTERVAL_ROOT && p > 0;
+            rT = (filt || MODE == kScanBridge) ? a.tree.rootT[gi] : 0.f;
             // inactive backward trees (root at or after U) are hidden behind a NaN time
-            if (!ok || (filt && !(rt < U))) tn = __int_as_float(0x7fc00000);
-            sx[lane][7] = sv * tn;
-            sT[lane] = rt;
-            __syncthreads();
-            const int m = (int)min<int64_t>(kScanThreads, c1 - c);
-            if (act) {
-                for (int k = 0; k < m; ++k) {
-                    float D2 = 0.f;
+            if (filt && !(rT < U)) tn = nanf_;
+            rx[7] = sv * tn;
+            rI = (int32_t)gi;
+        }
+    };
+    if (c0 < c1) fetch(c0);
+    for (int64_t c = c0; c < c1; c += kTileQ) {
+        __syncthreads();
 #pragma unroll
-                    for (int j = 0; j < kMaxDof; ++j) {
-                        if (j < d) {
-                            const float e = sx[k][j] - qx[j];
-                            D2 = fmaf(e, e, D2);
-                        }
+        for (int j = 0; j < 8; ++j) sx[tid][j] = rx[j];
+        sT[tid] = rT;
+        sI[tid] = rI;
+        __syncthreads();
+        if (c + kTileQ < c1) fetch(c + kTileQ);
+        const int m = (int)min<int64_t>(kTileQ, c1 - c);
+        if (act) {
+            for (int k = 0; k < m; ++k) {
+                float D2 = 0.f;
+#pragma unroll
+                for (int j = 0; j < kMaxDof; ++j) {
+                    if (j < d) {
+                        const float e = sx[k][j] - qx[j];
+                        D2 = fmaf(e, e, D2);
                     }
-                    if (MODE == kScanConfig) {
-                        if (D2 < best) { best = D2; bi = (int32_t)(base + c + k); }
+                }
+                if (MODE == kScanConfig) {
+                    if (D2 < best) { best = D2; bi = sI[k]; }
+                } else {
+                    // Eq. 7: admissible iff sigma (t_q - t) > 0 and D <= v sigma (t_q - t)
+                    const float vd = aq - sx[k][7];
+                    const float w2 = vd * fabsf(vd);
+                    const bool adm = (D2 <= w2) && (w2 > 0.f);
+                    const float key = D2 + w2;
+                    if (MODE == kScanRho) {
+                        if (adm && key < best) { best = key; bi = sI[k]; }
                     } else {
-                        // Eq. 7: admissible iff sigma (t_q - t) > 0 and D <= v sigma (t_q - t)
-                        const float vd = aq - sx[k][7];
-                        const float w2 = vd * fabsf(vd);
-                        const bool adm = (D2 <= w2) && (w2 > 0.f);
-                        const float key = D2 + w2;
-                        if (MODE == kScanRho) {
-                            if (adm && key < best) { best = key; bi = (int32_t)(base + c + k); }
-                        } else {
-                            const float arr = set < 0 ? sT[k] : 0.f;
-                            if (adm && (arr < bestT || (arr == bestT && key < best))) {
-                                bestT = arr;
-                                best = key;
-                                bi = (int32_t)(base + c + k);
-                            }
+                        const float arr = set < 0 ? sT[k] : 0.f;
+                        if (adm && (arr < bestT || (arr == bestT && key < best))) {
+                            bestT = arr;
+                            best = key;
+                            bi = sI[k];
                         }
                     }
                 }
             }
-            __syncthreads();
         }
     }
     if (!act) return;
     if (MODE == kScanBridge) {
-        a.pkey[(int64_t)y * a.pstride + q] = bi < 0 ? kNoKey : (((unsigned long long)__float_as_uint(bestT) << 32) |
-                                                                 __float_as_uint(best));
-        a.pidx[(int64_t)y * a.pstride + q] = bi;
+        a.pkey[(int64_t)blockIdx.y * a.pstride + q] =
+            bi < 0 ? kNoKey : (((unsigned long long)__float_as_uint(bestT) << 32) | __float_as_uint(best));
+        a.pidx[(int64_t)blockIdx.y * a.pstride + q] = bi;
     } else if (bi >= 0) {
         atomicMin(&a.keys[q], pack_key(best, bi));
     }
@@ -551,26 +672,37 @@ struct BridgeArgs {
 };
 
 __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // one wave per worker: lane y reads the y-th slice's best candidate
+    const int lane = threadIdx.x & 63;
+    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (w >= a.B) return;
     Work &k = a.w;
     const int d = a.tree.d, W = d + 1;
+    const bool adv = k.status[w] == ST_STATUS_ADVANCED;
+    unsigned long long bk = kNoKey;
+    uint32_t bi = 0xffffffffu;
+    if (adv && lane < a.nch) {
+        const int32_t ii = k.br_idx[(int64_t)lane * a.B + w];
+        if (ii >= 0) {
+            bk = k.br_key[(int64_t)lane * a.B + w];
+            bi = (uint32_t)ii;
+        }
+    }
+    // lexicographic (key, index) minimum over the wave
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ok = __shfl_xor(bk, o, 64);
+        const uint32_t oi = __shfl_xor(bi, o, 64);
+        if (ok < bk || (ok == bk && oi < bi)) {
+            bk = ok;
+            bi = oi;
+        }
+    }
+    if (lane != 0) return;
     k.bridge[w] = -1;
     k.br_valid[w] = 0;
     k.Up[w] = INFINITY;
     k.Cp[w] = INFINITY;
-    if (k.status[w] != ST_STATUS_ADVANCED) return;
-    unsigned long long bk = kNoKey;
-    int32_t bi = -1;
-    for (int y = 0; y < a.nch; ++y) {
-        const unsigned long long kk = k.br_key[(int64_t)y * a.B + w];
-        const int32_t ii = k.br_idx[(int64_t)y * a.B + w];
-        if (ii >= 0 && (kk < bk || (kk == bk && (uint32_t)ii < (uint32_t)bi))) {
-            bk = kk;
-            bi = ii;
-        }
-    }
-    if (bi < 0) return;
+    if (!adv || bi == 0xffffffffu) return;
     float D2 = 0.f;
     for (int j = 0; j <= d; ++j) {
         const float v = a.tree.x[(int64_t)j * a.tree.total + bi];
@@ -580,7 +712,7 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a) {
             D2 = fmaf(e, e, D2);
         }
     }
-    k.bridge[w] = bi;
+    k.bridge[w] = (int32_t)bi;
     k.br_valid[w] = 1;
     k.Up[w] = a.dir[w] == 0 ? a.tree.rootT[bi] : k.rootT_new[w];
     k.Cp[w] = k.cost_new[w] + sqrtf(D2) + a.tree.cost[bi];
@@ -789,6 +921,43 @@ __global__ __launch_bounds__(256) void k_roots(RootsArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// learned proposal parameters from the network output z
+// ---------------------------------------------------------------------------
+
+__global__ void k_prop_set(PlanDev *pl, const float *z, float mix) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!z || !(mix > 0.f)) {
+        pl->prop_mix = 0.f;
+        return;
+    }
+    float mx = -INFINITY;
+    for (int c = 0; c < 8; ++c) mx = fmaxf(mx, z[c]);
+    float s = 0.f;
+    for (int c = 0; c < 8; ++c) s += expf(z[c] - mx);
+    float acc = 0.f;
+    for (int c = 0; c < 8; ++c) {
+        acc += expf(z[c] - mx) / s;
+        pl->prop_wcum[c] = acc;
+    }
+    pl->prop_wcum[7] = 1.f;
+    for (int i = 0; i < 64; ++i) {
+        pl->prop_mu[i] = z[8 + i];
+        pl->prop_sd[i] = expf(z[72 + i]);
+    }
+    mx = -INFINITY;
+    for (int b = 0; b < 32; ++b) mx = fmaxf(mx, z[136 + b]);
+    s = 0.f;
+    for (int b = 0; b < 32; ++b) s += expf(z[136 + b] - mx);
+    acc = 0.f;
+    for (int b = 0; b < 32; ++b) {
+        acc += expf(z[136 + b] - mx) / s;
+        pl->prop_hcum[b] = acc;
+    }
+    pl->prop_hcum[31] = 1.f;
+    pl->prop_mix = mix;
+}
+
+// ---------------------------------------------------------------------------
 // nearest-node results for the C ABI
 // ---------------------------------------------------------------------------
 
@@ -806,8 +975,8 @@ __global__ void k_nn_out(int64_t M, int metric, const unsigned long long *keys, 
 
 __global__ void k_fill_tiles(int64_t M, int set, int sigma, int4 *tiles, int32_t *n_tiles, unsigned long long *keys) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t nt = (M + kScanThreads - 1) / kScanThreads;
-    if (i < nt) tiles[i] = make_int4(set, (int)(i * kScanThreads), (int)min<int64_t>(kScanThreads, M - i * kScanThreads), sigma);
+    const int64_t nt = (M + kTileQ - 1) / kTileQ;
+    if (i < nt) tiles[i] = make_int4(set, (int)(i * kTileQ), (int)min<int64_t>(kTileQ, M - i * kTileQ), sigma);
     if (i == 0) n_tiles[0] = (int32_t)nt;
     for (int64_t j = i; j < M; j += (int64_t)gridDim.x * blockDim.x) keys[j] = kNoKey;
 }
@@ -849,18 +1018,16 @@ using IC = std::integral_constant<int, V>;
 static int ot_for(int O_pad) {
     if (O_pad <= 4) return 4;
     if (O_pad <= 8) return 8;
-    if (O_pad <= 16) return 16;
-    return 32;
+    return 16;
 }
 
 template <class F>
 static void dispatch_scene2(const SceneDev &sc, F &&f) {
     auto by_ot = [&](auto kind, auto obs) {
-        switch (ot_for(sc.O_pad)) {
+        switch (sc.ot) {
             case 4: f(kind, IC<4>{}, obs); break;
             case 8: f(kind, IC<8>{}, obs); break;
-            case 16: f(kind, IC<16>{}, obs); break;
-            default: f(kind, IC<32>{}, obs); break;
+            default: f(kind, IC<16>{}, obs); break;
         }
     };
     auto by_obs = [&](auto kind) {
@@ -886,11 +1053,12 @@ void work_free(st_problem *p) {
     memset(&w, 0, sizeof w);
 }
 
-static int max_tiles(int64_t B, int n_sets) { return (int)((B + kScanThreads - 1) / kScanThreads) + n_sets; }
+static int max_tiles(int64_t B, int n_sets) { return (int)((B + kTileQ - 1) / kTileQ) + n_sets; }
 
 int work_reserve(st_problem *p, int64_t B) {
     if (p->work.Bcap >= B) return ST_OK;
     ST_HIP(hipDeviceSynchronize());
+    graphs_free(p);
     work_free(p);
     Work &w = p->work;
     const int W = p->d + 1;
@@ -930,8 +1098,9 @@ int work_reserve(st_problem *p, int64_t B) {
     return ST_OK;
 }
 
+// Node slices per tile: enough blocks to fill the 256 CUs a few times over.
 static int nch_for(int tiles) {
-    int n = 2048 / std::max(tiles, 1);
+    int n = 1024 / std::max(tiles, 1);
     return std::max(1, std::min(kMaxNch, n));
 }
 
@@ -962,6 +1131,8 @@ int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, 
     a.pid = p->prm.problem_id;
     a.iter = iter;
     a.B = B;
+    a.t_min = p->t_min;
+    a.t_max = p->t_max;
     a.out = out;
     const int blocks = (int)((B + 255) / 256);
     const size_t lds = scene_lds_bytes(p->sc);
@@ -973,17 +1144,15 @@ int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, 
     return ST_OK;
 }
 
-static int edge_shift(const st_problem *p, bool bridge) {
-    if (bridge) return 6;
-    const double n_typ = p->prm.eta / p->prm.h + 1.0;
-    int shift = 3;
-    while ((1 << shift) < n_typ && shift < 6) ++shift;
-    return shift;
-}
+static int edge_shift(const st_problem *p, bool bridge) { return bridge ? p->tune_br : p->tune_ext; }
 
 int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s) {
     int rc = work_reserve(p, B);
     if (rc != ST_OK) return rc;
+    if (p->ebufs.cap < B) {
+        graphs_free(p);
+        if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
+    }
     Work &w = p->work;
     const int np = p->tree.n_pools;
     const int d = p->d;
@@ -1021,9 +1190,9 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     sa.keys = w.nn_key;
     sa.nch = nch_for(mt_nn);
     if (p->prm.variant == ST_INTERVAL_ROOT)
-        k_scan<kScanRho><<<dim3(mt_nn, sa.nch), kScanThreads, 0, s>>>(sa);
+        k_scan<kScanRho><<<dim3(mt_nn, sa.nch), kTileQ, 0, s>>>(sa);
     else
-        k_scan<kScanConfig><<<dim3(mt_nn, sa.nch), kScanThreads, 0, s>>>(sa);
+        k_scan<kScanConfig><<<dim3(mt_nn, sa.nch), kTileQ, 0, s>>>(sa);
     ST_HIP(hipGetLastError());
     // steering (a3)
     SteerArgs ta;
@@ -1041,8 +1210,8 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     ST_HIP(hipGetLastError());
     // extension edge checks (a4)
     prof_mark(p, kStEdge, s);
-    ST_HIP(launch_check_edges(p->sc, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit, edge_shift(p, false), s,
-                              p->d_plan->work));
+    ST_HIP(launch_check_edges(p->sc, p->ebufs, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit,
+                              edge_shift(p, false), s, p->d_plan->work));
     prof_mark(p, kStInsert, s);
     // insertion (a5)
     InsertArgs ia;
@@ -1070,7 +1239,7 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     sb.pidx = w.br_idx;
     sb.pstride = B;
     sb.nch = nch_for(mt_br);
-    k_scan<kScanBridge><<<dim3(mt_br, sb.nch), kScanThreads, 0, s>>>(sb);
+    k_scan<kScanBridge><<<dim3(mt_br, sb.nch), kTileQ, 0, s>>>(sb);
     ST_HIP(hipGetLastError());
     BridgeArgs ba;
     ba.tree = p->tree;
@@ -1078,11 +1247,11 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     ba.nch = sb.nch;
     ba.dir = in.dir;
     ba.w = w;
-    k_bridge_merge<<<blocks, 256, 0, s>>>(ba);
+    k_bridge_merge<<<(int)((B * 64 + 255) / 256), 256, 0, s>>>(ba);
     ST_HIP(hipGetLastError());
     prof_mark(p, kStBridgeEdge, s);
-    ST_HIP(launch_check_edges(p->sc, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true), s,
-                              p->d_plan->work + 2));
+    ST_HIP(launch_check_edges(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit,
+                              edge_shift(p, true), s, p->d_plan->work + 2));
     prof_mark(p, kStPublish, s);
     // publish (a7)
     PublishArgs pb;
@@ -1119,7 +1288,7 @@ int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64
     int rc = work_reserve(p, M);
     if (rc != ST_OK) return rc;
     Work &w = p->work;
-    const int nt = (int)((M + kScanThreads - 1) / kScanThreads);
+    const int nt = (int)((M + kTileQ - 1) / kTileQ);
     k_fill_tiles<<<(nt + 255) / 256, 256, 0, s>>>(M, set < 0 ? (set == ST_SET_FORWARD ? 0 : kSetAllBackward) : 1 + set,
                                                  sigma, (int4 *)w.tiles, w.n_tiles, w.nn_key);
     ST_HIP(hipGetLastError());
@@ -1136,8 +1305,8 @@ int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64
     sa.n_tiles = w.n_tiles;
     sa.keys = w.nn_key;
     sa.nch = nch_for(nt);
-    if (metric == ST_METRIC_RHO) k_scan<kScanRho><<<dim3(nt, sa.nch), kScanThreads, 0, s>>>(sa);
-    else k_scan<kScanConfig><<<dim3(nt, sa.nch), kScanThreads, 0, s>>>(sa);
+    if (metric == ST_METRIC_RHO) k_scan<kScanRho><<<dim3(nt, sa.nch), kTileQ, 0, s>>>(sa);
+    else k_scan<kScanConfig><<<dim3(nt, sa.nch), kTileQ, 0, s>>>(sa);
     ST_HIP(hipGetLastError());
     k_nn_out<<<(int)((M + 255) / 256), 256, 0, s>>>(M, metric, w.nn_key, idx_out, dist_out);
     ST_HIP(hipGetLastError());
@@ -1156,16 +1325,85 @@ static st_samples work_samples(st_problem *p) {
     return s;
 }
 
+void graphs_free(st_problem *p) {
+    for (int k = 0; k < 2; ++k) {
+        if (p->graph[k]) (void)hipGraphExecDestroy(p->graph[k]);
+        p->graph[k] = nullptr;
+    }
+    p->graph_B = 0;
+}
+
+// Capture `n` iterations (sample + extend batch, all kernels) into an
+// executable graph on the problem's capture stream.  The kernels read the
+// iteration number and every size they need from device memory, so one graph
+// serves every later iteration.
+static int capture_iterations(st_problem *p, int n, hipGraphExec_t *out) {
+    const int64_t B = p->prm.batch;
+    const st_samples smp = work_samples(p);
+    if (!p->cap_stream) ST_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    hipStream_t cs = p->cap_stream;
+    ST_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = ST_OK;
+    for (int i = 0; i < n && rc == ST_OK; ++i) {
+        rc = sample_batch(p, -1, B, smp, cs);
+        if (rc == ST_OK) rc = extend_batch(p, B, smp, nullptr, cs);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != ST_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        set_error("graph capture failed: %s", hipGetErrorString(e));
+        return ST_EHIP;
+    }
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        set_error("graph instantiation failed: %s", hipGetErrorString(e2));
+        return ST_EHIP;
+    }
+    return ST_OK;
+}
+
+constexpr int kGraphChunk = 4;
+
 static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
     const int64_t B = p->prm.batch;
     int rc = work_reserve(p, B);
     if (rc != ST_OK) return rc;
-    const st_samples smp = work_samples(p);
-    for (int64_t i = 0; i < iters; ++i) {
-        if ((rc = sample_batch(p, p->iter, B, smp, s)) != ST_OK) return rc;
-        if ((rc = extend_batch(p, B, smp, nullptr, s)) != ST_OK) return rc;
-        p->iter++;
+    if (p->ebufs.cap < B) {
+        graphs_free(p);
+        if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
     }
+    if (p->prof || !p->use_graphs) {
+        // eager launches (stage timing records events between kernels)
+        const st_samples smp = work_samples(p);
+        for (int64_t i = 0; i < iters; ++i) {
+            if ((rc = sample_batch(p, -1, B, smp, s)) != ST_OK) return rc;
+            if ((rc = extend_batch(p, B, smp, nullptr, s)) != ST_OK) return rc;
+            p->iter++;
+        }
+        return ST_OK;
+    }
+    if (p->graph_B != B || !p->graph[0] || !p->graph[1]) {
+        graphs_free(p);
+        ST_HIP(hipDeviceSynchronize());
+        if ((rc = capture_iterations(p, 1, &p->graph[0])) != ST_OK) return rc;
+        if ((rc = capture_iterations(p, kGraphChunk, &p->graph[1])) != ST_OK) return rc;
+        p->graph_B = B;
+    }
+    int64_t left = iters;
+    while (left >= kGraphChunk) {
+        ST_HIP(hipGraphLaunch(p->graph[1], s));
+        left -= kGraphChunk;
+    }
+    while (left > 0) {
+        ST_HIP(hipGraphLaunch(p->graph[0], s));
+        --left;
+    }
+    p->iter += iters;
     return ST_OK;
 }
 
@@ -1214,6 +1452,16 @@ int st_extend_batch(st_problem *p, int64_t B, const st_samples *s, const st_exte
     int rc = extend_batch(p, B, *s, o, (hipStream_t)stream);
     if (rc == ST_OK) p->iter++;
     return rc;
+}
+
+int st_proposal_set(st_problem *p, const float *z, float mix, void *stream) {
+    if (!p || !(mix >= 0.f && mix <= 1.f)) {
+        set_error("st_proposal_set: bad arguments");
+        return ST_EINVAL;
+    }
+    k_prop_set<<<1, 1, 0, (hipStream_t)stream>>>(p->d_plan, z, mix);
+    ST_HIP(hipGetLastError());
+    return ST_OK;
 }
 
 int st_iterate(st_problem *p, int64_t iters, void *stream) {

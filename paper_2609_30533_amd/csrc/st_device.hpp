@@ -9,9 +9,10 @@
 //           cost[total], rootT[total]; pool p occupies [base(p), base(p)+cap(p)).
 //
 // The collision test keeps one space-time state per lane.  Forward kinematics
-// runs in registers; uniform robot data (sphere offsets, DH constants, the pair
-// table) is read through scalar loads; obstacle centres at the lane's own time
-// come from the segment table staged in LDS.  A pair collides iff
+// runs in registers with the DH constants from the kernel arguments; sphere
+// offsets and the pair table are staged in LDS and read as broadcasts;
+// obstacle centres at the lane's own time come from the segment table, also
+// staged in LDS.  A pair collides iff
 //   |c|^2 + |o|^2 - 2 c.o < (r_s + r_o)^2,
 // evaluated as a_s + b_o + c.n with n = -2 o (four FMA-class ops and a compare).
 #pragma once
@@ -34,6 +35,8 @@ constexpr double kClearanceEps = 2e-5;
 
 struct SceneDev {
     int d, kind, S, O, O_pad, n_seg, obs_mode, lds_f4;  // lds_f4: float4 slots staged in LDS
+    int lds_sph, lds_r2, lds_t;  // float4 offsets in LDS of the spheres, the pair table, the times
+    int ot;                      // obstacles per register tile (4, 8 or 16; divides O_pad)
     float v, H, h, inv_h;
     double v_d, h_d;
     float q_lo[8], q_hi[8], q_s[8], q_g[8];
@@ -45,13 +48,16 @@ struct SceneDev {
     const float *seg_t;         // shared mode: [n_seg+1]; generic: [O_pad][n_seg+1]
 };
 
-// Stage the obstacle segment table (and, in generic mode, the waypoint times)
-// into LDS.  Every thread of the block must call it.
+// Stage the scene into LDS: obstacle segment table, robot spheres, pair table
+// and (generic mode) waypoint times.  Every thread of the block must call it.
 __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds) {
     const int n = sc.O_pad * sc.n_seg * 2;
     for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = sc.seg[i];
+    for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_sph + i] = sc.sph[i];
+    float *r2 = reinterpret_cast<float *>(lds + sc.lds_r2);
+    for (int i = threadIdx.x; i < sc.S * sc.O_pad; i += blockDim.x) r2[i] = sc.R2[i];
     if (sc.obs_mode == kObsGeneric) {
-        float *lt = reinterpret_cast<float *>(lds + n);
+        float *lt = reinterpret_cast<float *>(lds + sc.lds_t);
         const int m = sc.O_pad * (sc.n_seg + 1);
         for (int i = threadIdx.x; i < m; i += blockDim.x) lt[i] = sc.seg_t[i];
     }
@@ -78,10 +84,44 @@ __device__ __forceinline__ void obstacle_n(const float4 *lds, int n_seg, int o, 
 }
 
 __device__ __forceinline__ int generic_segment(const SceneDev &sc, const float4 *lds, int o, float t) {
-    const float *lt = reinterpret_cast<const float *>(lds + sc.O_pad * sc.n_seg * 2) + o * (sc.n_seg + 1);
+    const float *lt = reinterpret_cast<const float *>(lds + sc.lds_t) + o * (sc.n_seg + 1);
     int k = 0;
     for (int j = 1; j < sc.n_seg; ++j) k += (t >= lt[j]) ? 1 : 0;
     return k;
+}
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Sphere s (centre c, a_s = |c|^2) against the OT obstacles of the tile:
+// a_s + b_o + c.n < (r_s + r_o)^2 for any o.  The radii row is read as float4
+// broadcasts; each compare's lane mask (the ballot of the active lanes) is
+// OR-ed on the scalar unit, so the loop is straight-line code with one add,
+// three FMAs and one compare per pair.  Returns the wave mask of hits.
+template <int OT>
+__device__ __forceinline__ uint64_t pair_hits(const float4 *lds, const SceneDev &sc, int s, int tile, float cx,
+                                              float cy, float cz, float as, const float *nx, const float *ny,
+                                              const float *nz, const float *bo) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(lds + sc.lds_r2) +
+                                                        s * sc.O_pad + tile);
+    float r2[OT];
+#pragma unroll
+    for (int i = 0; i < OT / 4; ++i) {
+        const float4 v = r4[i];
+        r2[4 * i] = v.x;
+        r2[4 * i + 1] = v.y;
+        r2[4 * i + 2] = v.z;
+        r2[4 * i + 3] = v.w;
+    }
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < OT; ++i) {
+        float v = as + bo[i];
+        v = fmaf(cx, nx[i], v);
+        v = fmaf(cy, ny[i], v);
+        v = fmaf(cz, nz[i], v);
+        m |= __ballot(v < r2[i]);
+    }
+    return m;
 }
 
 // Does the lane's state (q, t) collide?  OT obstacles are held in registers
@@ -95,6 +135,7 @@ template <int KIND, int OT, int OBS, bool FIRST>
 __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds, const float *q, float t, bool alive,
                                            uint64_t group_mask, uint64_t lower_mask) {
     bool hit = false;
+    uint64_t hm = 0;  // wave mask of lanes with a colliding pair
     // configuration box and horizon
     if (alive) {
         bool out = !(t >= 0.0f) || !(t <= sc.H);
@@ -110,15 +151,6 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
     }
     int kseg = 0;
     if (OBS == kObsShared) kseg = shared_segment(sc, t);
-    // sines and cosines of the joint angles, once per state
-    float sn[kMaxDof], cs[kMaxDof];
-    if (KIND == kDH) {
-#pragma unroll
-        for (int j = 0; j < kMaxDof; ++j) {
-            if (j < sc.d) __sincosf(q[j] + sc.dh_t0[j], &sn[j], &cs[j]);
-            else { sn[j] = 0.0f; cs[j] = 1.0f; }
-        }
-    }
     for (int tile = 0; tile < sc.O_pad; tile += OT) {
         if (__ballot(alive) == 0) break;
         float nx[OT], ny[OT], nz[OT], bo[OT];
@@ -135,20 +167,13 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
             const float px = q[0], py = q[1], pz = sc.d >= 3 ? q[2] : 0.0f;
             for (int s = 0; s < sc.S; ++s) {
                 if (alive) {
-                    const float4 sp = sc.sph[s];
+                    const float4 sp = lds[sc.lds_sph + s];
                     const float cx = px + sp.x, cy = py + sp.y, cz = pz + sp.z;
                     const float as = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
-                    const float *r2 = sc.R2 + s * sc.O_pad + tile;
-#pragma unroll
-                    for (int i = 0; i < OT; ++i) {
-                        float v = as + bo[i];
-                        v = fmaf(cx, nx[i], v);
-                        v = fmaf(cy, ny[i], v);
-                        v = fmaf(cz, nz[i], v);
-                        hit = hit || (v < r2[i]);
-                    }
+                    hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
                 }
             }
+            hit = hit || ((hm >> lane_id()) & 1ull);
             const uint64_t m = __ballot(hit);
             if (FIRST) alive = alive && !hit && !(m & lower_mask);
             else alive = alive && !(m & group_mask);
@@ -161,7 +186,8 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
                 if (l > sc.d) break;
                 if (l > 0 && alive) {
                     // T <- T * Rz(theta) Tz(d) Tx(a) Rx(alpha)
-                    const float ct = cs[l - 1], st_ = sn[l - 1];
+                    float st_, ct;
+                    __sincosf(q[l - 1] + sc.dh_t0[l - 1], &st_, &ct);
                     const float ca = sc.dh_ca[l - 1], sa = sc.dh_sa[l - 1];
                     const float a = sc.dh_a[l - 1], dd = sc.dh_d[l - 1];
                     float u, w;
@@ -179,22 +205,15 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
                 if (s1 > s0 && __ballot(alive) != 0) {
                     for (int s = s0; s < s1; ++s) {
                         if (alive) {
-                            const float4 sp = sc.sph[s];
+                            const float4 sp = lds[sc.lds_sph + s];
                             const float cx = fmaf(R00, sp.x, fmaf(R01, sp.y, fmaf(R02, sp.z, p0)));
                             const float cy = fmaf(R10, sp.x, fmaf(R11, sp.y, fmaf(R12, sp.z, p1)));
                             const float cz = fmaf(R20, sp.x, fmaf(R21, sp.y, fmaf(R22, sp.z, p2)));
                             const float as = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
-                            const float *r2 = sc.R2 + s * sc.O_pad + tile;
-#pragma unroll
-                            for (int i = 0; i < OT; ++i) {
-                                float v = as + bo[i];
-                                v = fmaf(cx, nx[i], v);
-                                v = fmaf(cy, ny[i], v);
-                                v = fmaf(cz, nz[i], v);
-                                hit = hit || (v < r2[i]);
-                            }
+                            hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
                         }
                     }
+                    hit = hit || ((hm >> lane_id()) & 1ull);
                     const uint64_t m = __ballot(hit);
                     if (FIRST) alive = alive && !hit && !(m & lower_mask);
                     else alive = alive && !(m & group_mask);

@@ -53,6 +53,14 @@ struct PlanDev {
     // work counters: [0] extension edges decided, [1] their states up to the
     // first hit (n+1 when free), [2] bridge edges decided, [3] their states
     unsigned long long work[4];
+    // learned proposal: probability of a learned draw, cumulative mixture
+    // weights, means and standard deviations (normalised), cumulative
+    // arrival-histogram weights
+    float prop_mix;
+    float prop_wcum[8];
+    float prop_mu[64];
+    float prop_sd[64];
+    float prop_hcum[32];
 };
 
 // Node pools in device memory, SoA.
@@ -79,6 +87,16 @@ struct WindowsDev {
     int32_t N;
     int32_t k_lo, k_hi;
     const uint8_t *gfree;         // goal grid, [k_hi - k_lo + 1]
+};
+
+// Work buffers of the edge-check pipeline (capacity cap edges).
+struct EdgeBufs {
+    int64_t cap = 0;
+    int32_t mmax = 0;           // work items per edge at most (<= 16)
+    int32_t *n = nullptr;       // [cap] state count, -1 for skipped edges
+    int32_t *hit = nullptr;     // [cap] least colliding state index found
+    int2 *items = nullptr;      // [mmax][cap] (edge, rank)
+    int32_t *cnt = nullptr;     // [16] items per rank list
 };
 
 // Per-batch work buffers (capacity Bcap workers).
@@ -134,8 +152,17 @@ struct st_problem {
     st::TreeDev tree{};
     st::PlanDev *d_plan = nullptr;
     st::Work work{};
+    st::EdgeBufs ebufs{};      // planner edge checks (referenced by captured graphs)
+    st::EdgeBufs ebufs_api{};  // st_check_edges
     int64_t iter = 0;
     int nch = 16;  // node chunks per query tile in scans
+    // captured iterations: [0] one iteration, [1] four iterations
+    bool use_graphs = true;
+    // lanes per edge chunk (log2) for extension, bridge and st_check_edges launches
+    int tune_ext = 5, tune_br = 6, tune_api = 5;
+    hipGraphExec_t graph[2] = {nullptr, nullptr};
+    int64_t graph_B = 0;
+    hipStream_t cap_stream = nullptr;
     // optional stage timing with HIP events (stage id per recorded event)
     bool prof = false;
     std::vector<hipEvent_t> prof_ev;
@@ -148,10 +175,12 @@ namespace st {
 // ---- collision ------------------------------------------------------------
 size_t scene_lds_bytes(const SceneDev &sc);
 hipError_t launch_check_states(const SceneDev &sc, int64_t M, const float *x, uint8_t *free_out, hipStream_t s);
-// Lanes per edge = 1 << lpe_shift (1..64).  first_hit may be null (any-hit exit).
-hipError_t launch_check_edges(const SceneDev &sc, int64_t E, const float *xa, const float *xb, const uint8_t *valid,
-                              uint8_t *free_out, int32_t *first_hit, int lpe_shift, hipStream_t s,
-                              unsigned long long *work = nullptr);
+int edge_bufs_reserve(EdgeBufs &eb, int64_t E);
+void edge_bufs_free(EdgeBufs &eb);
+// Lanes per chunk = 1 << lpe_shift (1..64).  first_hit and work may be null.
+hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
+                              const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
+                              hipStream_t s, unsigned long long *work = nullptr);
 
 // ---- stage timing ------------------------------------------------------------
 enum Stage { kStSample = 0, kStNearest, kStSteer, kStEdge, kStInsert, kStBridgeSel, kStBridgeEdge, kStPublish,
@@ -165,6 +194,7 @@ int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, 
 int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s);
 int work_reserve(st_problem *p, int64_t B);
 void work_free(st_problem *p);
+void graphs_free(st_problem *p);
 
 // ---- allocation ------------------------------------------------------------
 hipError_t launch_roots_update(st_problem *p, hipStream_t s);

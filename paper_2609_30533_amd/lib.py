@@ -80,8 +80,11 @@ EXPORTS = [
     "st_problem_create", "st_problem_destroy", "st_problem_reset", "st_check_states", "st_check_edges",
     "st_nearest", "st_sample_batch", "st_extend_batch", "st_iterate", "st_plan", "st_path_free", "st_get_info",
     "st_tree_export", "st_tree_import", "st_slots_export", "st_goal_grid_export", "st_partition_export",
-    "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
+    "st_set_tuning", "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
+    "st_mlp_create", "st_mlp_destroy", "st_mlp_param_count", "st_mlp_params", "st_mlp_grads", "st_mlp_forward",
+    "st_mlp_loss", "st_mlp_backward", "st_mlp_adam", "st_proposal_set",
 ]
+NO_INT_RESULT = ("st_problem_destroy", "st_path_free", "st_last_error", "st_mlp_destroy", "st_mlp_param_count")
 STAGES = ["sample", "nearest", "steer", "edge_check", "insert", "bridge_select", "bridge_check", "publish"]
 
 _lib = None
@@ -118,13 +121,26 @@ def load():
     L.st_slots_export.argtypes = [vp, vp, vp, vp, vp]
     L.st_goal_grid_export.argtypes = [vp, vp]
     L.st_partition_export.argtypes = [vp, vp, vp, vp, i32]
+    L.st_set_tuning.argtypes = [vp, i32, i32, i32, i32]
     L.st_profile_enable.argtypes = [vp, i32]
     L.st_profile_read.argtypes = [vp, vp, vp]
     L.st_work_counters.argtypes = [vp, vp]
     L.st_last_error.argtypes = []
     L.st_last_error.restype = C.c_char_p
+    L.st_mlp_create.argtypes = [i32, i32, C.POINTER(vp)]
+    L.st_mlp_destroy.argtypes = [vp]
+    L.st_mlp_destroy.restype = None
+    L.st_mlp_param_count.argtypes = []
+    L.st_mlp_param_count.restype = i64
+    L.st_mlp_params.argtypes = [vp, vp, vp]
+    L.st_mlp_grads.argtypes = [vp, vp]
+    L.st_mlp_forward.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp]
+    L.st_mlp_loss.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+    L.st_mlp_backward.argtypes = [vp, vp]
+    L.st_mlp_adam.argtypes = [vp, C.c_float, vp]
+    L.st_proposal_set.argtypes = [vp, vp, C.c_float, vp]
     for name in EXPORTS:
-        if name not in ("st_problem_destroy", "st_path_free", "st_last_error"):
+        if name not in NO_INT_RESULT:
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -322,6 +338,15 @@ class Problem:
         _check(self.L.st_tree_import(self.h, _ptr(counts), _ptr(x), _ptr(parent), _ptr(cost), _ptr(rootT), float(U),
                                      float(Cst), int(inc_f), int(inc_b), int(it), *sp), "st_tree_import")
 
+    def set_tuning(self, obstacle_tile=0, lanes_extension=0, lanes_bridge=0, lanes_check=0):
+        _check(self.L.st_set_tuning(self.h, obstacle_tile, lanes_extension, lanes_bridge, lanes_check),
+               "st_set_tuning")
+
+    def set_proposal(self, z=None, mix=0.5, stream=None):
+        """Install the network output z (device tensor [168]) for this problem."""
+        _check(self.L.st_proposal_set(self.h, _dptr(z), float(mix if z is not None else 0.0), _stream(stream)),
+               "st_proposal_set")
+
     def profile(self, enable=True):
         _check(self.L.st_profile_enable(self.h, 1 if enable else 0), "st_profile_enable")
 
@@ -358,3 +383,65 @@ class Problem:
         _check(self.L.st_partition_export(self.h, _ptr(I), _ptr(npc), _ptr(pieces), maxp), "st_partition_export")
         pieces = pieces.reshape(self.N, maxp, 2)
         return I.reshape(self.N, 2), [pieces[i, :npc[i]].copy() for i in range(self.N)]
+
+
+class Mlp:
+    """The proposal network on the device (st_mlp_*)."""
+
+    def __init__(self, max_batch, max_obstacles=32):
+        self.L = load()
+        h = C.c_void_p()
+        _check(self.L.st_mlp_create(max_batch, max_obstacles, C.byref(h)), "st_mlp_create")
+        self.h = h
+        self.n_params = int(self.L.st_mlp_param_count())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.st_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.n_params
+        _check(self.L.st_mlp_params(self.h, _ptr(flat), None), "st_mlp_params")
+
+    def get_params(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(self.L.st_mlp_params(self.h, None, _ptr(out)), "st_mlp_params")
+        return out
+
+    def grads(self):
+        out = np.zeros(self.n_params, dtype=np.float32)
+        _check(self.L.st_mlp_grads(self.h, _ptr(out)), "st_mlp_grads")
+        return out
+
+    def forward(self, core, obs, mask, z_out=None, stream=None):
+        import torch
+        M, O = obs.shape[0], obs.shape[1]
+        z = z_out if z_out is not None else torch.empty(M, ST_MLP_OUTPUTS, dtype=torch.float32, device=core.device)
+        _check(self.L.st_mlp_forward(self.h, M, O, _dptr(core), _dptr(obs), _dptr(mask), _dptr(z), _stream(stream)),
+               "st_mlp_forward")
+        return z
+
+    def loss(self, y, ymask, dmask, ubin, stream=None):
+        import torch
+        M, K = y.shape[0], y.shape[1]
+        per = torch.empty(M, dtype=torch.float32, device=y.device)
+        _check(self.L.st_mlp_loss(self.h, K, _dptr(y), _dptr(ymask), _dptr(dmask), _dptr(ubin), _dptr(per),
+                                  _stream(stream)), "st_mlp_loss")
+        return per
+
+    def backward(self, stream=None):
+        _check(self.L.st_mlp_backward(self.h, _stream(stream)), "st_mlp_backward")
+
+    def adam(self, lr, stream=None):
+        _check(self.L.st_mlp_adam(self.h, float(lr), _stream(stream)), "st_mlp_adam")
+
+
+ST_MLP_OUTPUTS = 168

@@ -340,3 +340,60 @@ def synthetic_tree(prob: Problem, n_nodes: int, seed: int, sigma: int = 1):
         if n_nodes < 4096 else np.concatenate(
             [[-1], (rng.random(n_nodes - 1) * np.arange(1, n_nodes)).astype(np.int32)]).astype(np.int32)
     return q, t, parent
+
+
+# ----------------------------------------------------------------------------
+# Proposal-network feature rows (input formatting only)
+# ----------------------------------------------------------------------------
+
+PROP_CORE = 16           # q_s (7), q_g (7), t_min, t_max
+PROP_ENC_IN = 65         # 16 waypoints x (t, x, y, z), radius
+PROP_T_SCALE = 60.0      # seconds
+PROP_Q_SCALE = math.pi   # radians
+PROP_N_BINS = 32         # arrival-time histogram bins
+PROP_N_DIM = 8           # 7 joints + time
+
+
+def proposal_features(prob: Problem, o_max: int = 32):
+    """core [16], obs [o_max, 65], mask [o_max] describing one problem:
+    start and goal scaled by 1/pi, the arrival range and waypoint times by
+    1/60 s, each obstacle's first 16 waypoints (the last repeated) and radius."""
+    core = np.zeros(PROP_CORE)
+    core[:prob.d] = prob.q_start / PROP_Q_SCALE
+    core[7:7 + prob.d] = prob.q_goal / PROP_Q_SCALE
+    core[14] = prob.t_min / PROP_T_SCALE
+    core[15] = prob.t_max / PROP_T_SCALE
+    obs = np.zeros((o_max, PROP_ENC_IN))
+    mask = np.zeros(o_max)
+    for o in range(min(prob.n_obs, o_max)):
+        n = int(prob.n_wp[o])
+        for k in range(16):
+            w = prob.wp[o, min(k, n - 1)]
+            obs[o, 4 * k] = w[0] / PROP_T_SCALE
+            obs[o, 4 * k + 1:4 * k + 4] = w[1:4]
+        obs[o, 64] = prob.obs_r[o]
+        mask[o] = 1.0
+    return f32(core), f32(obs), mask
+
+
+def proposal_targets(prob: Problem, path: np.ndarray, K: int = 16):
+    """Training targets from one solution path (rows (q, t), start first):
+    y [K, 8] states at K evenly spaced path indices scaled like the features
+    (time in column 7, unused joints zero), ymask [K], dmask [8] (the robot's
+    joints and time) and the arrival bin of the path's last time over
+    [t_min, t_max] split into 32 equal bins."""
+    path = np.asarray(path, dtype=np.float64)
+    n = path.shape[0]
+    y = np.zeros((K, PROP_N_DIM))
+    ymask = np.zeros(K)
+    idx = np.unique(np.round(np.linspace(0, n - 1, min(K, n))).astype(int))
+    for k, i in enumerate(idx):
+        y[k, :prob.d] = path[i, :prob.d] / PROP_Q_SCALE
+        y[k, 7] = path[i, prob.d] / PROP_T_SCALE
+        ymask[k] = 1.0
+    dmask = np.zeros(PROP_N_DIM)
+    dmask[:prob.d] = 1.0
+    dmask[7] = 1.0
+    T = float(path[-1, prob.d])
+    b = int(math.floor((T - prob.t_min) / (prob.t_max - prob.t_min) * PROP_N_BINS))
+    return f32(y), ymask, dmask, min(max(b, 0), PROP_N_BINS - 1)
