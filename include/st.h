@@ -250,6 +250,44 @@ int st_plan(st_problem *p, const st_budget *budget, st_path *out);
 
 void st_path_free(st_path *path);
 
+/* The current incumbent path of a problem (host, library-allocated; free with
+ * st_path_free).  Returns ST_OK or ST_NO_SOLUTION.  Synchronous. */
+int st_path_get(st_problem *p, st_path *out);
+
+/* ---- many problems per launch (an addition to the paper's method) --------- */
+
+/* A batch runs one iteration of every member problem as one launch sequence:
+ * each kernel of the pipeline is launched once for all members (once per
+ * scene class for the two kernels specialised by robot kind, obstacle tile
+ * and obstacle-time mode), blockIdx.y selecting the member; `iters_per_launch`
+ * iterations are captured in one HIP graph.  The batch borrows the handles:
+ * they must outlive it and must not be iterated on their own while it exists.
+ * Each member keeps its own parameters (samples per iteration, launch shapes
+ * from st_set_tuning); changing them after st_batch_create has no effect on
+ * the batch.  Members whose start state collides, or that are trivial, take no
+ * part in the launches.  Synchronous. */
+typedef struct st_batch st_batch;
+int st_batch_create(st_problem *const *problems, int32_t n, int32_t iters_per_launch, st_batch **out);
+void st_batch_destroy(st_batch *b);
+/* `iters` iterations of every member (rounded up to whole launches).  Async. */
+int st_batch_iterate(st_batch *b, int64_t iters, void *stream);
+
+/* Per-member results of st_batch_plan; arrays are host memory owned by the
+ * caller, [n] each (any may be NULL). */
+typedef struct st_batch_result {
+    double *first_ms;      /* device time from the call's start to the end of the launch that found the
+                              member's first solution; NaN if none, 0 if it existed before the call */
+    int64_t *first_iter;   /* iteration of the first solution, -1 if none */
+    double *arrival;       /* incumbent arrival U, inf if none */
+    int64_t iterations;    /* out: iterations run by the call */
+    double total_ms;       /* out: wall time of the call */
+    int32_t n_solved;      /* out: members with an incumbent */
+} st_batch_result;
+/* Iterate every member within the budget (max_iters, max_ms; stop_at_first:
+ * until every member has a solution; iters_per_sync: iterations between host
+ * checks, rounded up to whole launches).  Synchronous. */
+int st_batch_plan(st_batch *b, const st_budget *budget, st_batch_result *res);
+
 /* ---- state I/O (tests) -------------------------------------------------- */
 
 int st_get_info(st_problem *p, st_info *out);

@@ -3,6 +3,7 @@
 //
 // One space-time state per lane; after each robot link the wave ballots its
 // hits so that lanes above a known hit of their group stop early.
+#include <algorithm>
 #include <type_traits>
 
 #include "st_internal.hpp"
@@ -51,15 +52,16 @@ __global__ __launch_bounds__(256) void k_check_states(SceneDev sc, int64_t M, co
 
 constexpr int32_t kNoHit = 0x7fffffff;
 
-__global__ __launch_bounds__(256) void k_edge_plan(int64_t E, int d, double v, double h, int L, int mmax,
-                                                   const float *__restrict__ xa, const float *__restrict__ xb,
-                                                   const uint8_t *__restrict__ valid, EdgeBufs eb) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
+    const EdgeBufs &eb = a.eb;
+    const int d = a.sc.d, L = 1 << a.lpe_shift, mmax = eb.mmax;
+    const double v = a.sc.v_d, h = a.sc.h_d;
+    const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const int w = d + 1;
     int m = 0;
-    if (e < E && !(valid && !valid[e])) {
-        const float *A = xa + e * w, *B = xb + e * w;
+    if (e < a.E && !(a.valid && !a.valid[e])) {
+        const float *A = a.xa + e * w, *B = a.xb + e * w;
         if (A[d] > B[d]) { const float *tmp = A; A = B; B = tmp; }
         double D2 = 0.0;
         for (int j = 0; j < d; ++j) {
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(256) void k_edge_plan(int64_t E, int d, double v, d
         m = (int)(c < mmax ? c : mmax);
         eb.n[e] = (int32_t)n;
         eb.hit[e] = kNoHit;
-    } else if (e < E) {
+    } else if (e < a.E) {
         eb.n[e] = -1;
     }
     for (int r = 0; r < mmax; ++r) {
@@ -93,15 +95,18 @@ __global__ __launch_bounds__(256) void k_edge_plan(int64_t E, int d, double v, d
 }
 
 template <int KIND, int OT, int OBS>
-__global__ __launch_bounds__(256) void k_edge_items(SceneDev sc, const float *__restrict__ xa,
-                                                    const float *__restrict__ xb, EdgeBufs eb, int lpe_shift) {
-    extern __shared__ float4 lds[];
+__device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, int bx, int nbx) {
+    const SceneDev &sc = a.sc;
+    const EdgeBufs &eb = a.eb;
+    const float *__restrict__ xa = a.xa;
+    const float *__restrict__ xb = a.xb;
     stage_obstacles(sc, lds);
     int32_t pre[17];
     pre[0] = 0;
     for (int r = 0; r < eb.mmax; ++r) pre[r + 1] = pre[r] + eb.cnt[r];
     const int64_t total = pre[eb.mmax];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lpe_shift = a.lpe_shift;
     const int lpe = 1 << lpe_shift;
     const int G = 64 >> lpe_shift;
     const int sub = lane & (lpe - 1), gsel = lane >> lpe_shift;
@@ -109,8 +114,8 @@ __global__ __launch_bounds__(256) void k_edge_items(SceneDev sc, const float *__
     const uint64_t group_mask = gbits << (gsel * lpe);
     const uint64_t lower_mask = group_mask & ((1ull << lane) - 1ull);
     const int w = sc.d + 1;
-    const int64_t stride = (int64_t)gridDim.x * (blockDim.x >> 6) * G;
-    for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * G; base < total; base += stride) {
+    const int64_t stride = (int64_t)nbx * (blockDim.x >> 6) * G;
+    for (int64_t base = ((int64_t)bx * (blockDim.x >> 6) + wave) * G; base < total; base += stride) {
         const int64_t v = base + gsel;
         bool done = !(v < total);
         int e = 0, rank = 0;
@@ -166,33 +171,65 @@ __global__ __launch_bounds__(256) void k_edge_items(SceneDev sc, const float *__
     }
 }
 
-__global__ __launch_bounds__(256) void k_edge_finish(int64_t E, const uint8_t *__restrict__ valid, EdgeBufs eb,
-                                                     uint8_t *__restrict__ free_out, int32_t *__restrict__ fh_out,
-                                                     unsigned long long *__restrict__ work) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
+    const EdgeBufs &eb = a.eb;
+    const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
     unsigned long long states = 0, edges = 0;
-    if (e < E && !(valid && !valid[e])) {
+    if (e < a.E && !(a.valid && !a.valid[e])) {
         const int32_t h = eb.hit[e];
         const bool fr = h == kNoHit;
-        free_out[e] = fr ? 1 : 0;
-        if (fh_out) fh_out[e] = fr ? -1 : h;
+        a.free_out[e] = fr ? 1 : 0;
+        if (a.first_hit) a.first_hit[e] = fr ? -1 : h;
         // algorithmic work: the states up to the first hit, all n+1 when free
         states = fr ? (unsigned long long)eb.n[e] + 1ull : (unsigned long long)h + 1ull;
         edges = 1;
     }
-    if (work) {
+    if (a.work) {
         for (int o = 32; o > 0; o >>= 1) {
             states += __shfl_down(states, o, 64);
             edges += __shfl_down(edges, o, 64);
         }
         if (lane == 0 && edges) {
-            atomicAdd(&work[0], edges);
-            atomicAdd(&work[1], states);
+            atomicAdd(&a.work[0], edges);
+            atomicAdd(&a.work[1], states);
         }
     }
     // the rank lists are consumed: leave them empty for the next launch
-    if (blockIdx.x == 0 && threadIdx.x < eb.mmax) eb.cnt[threadIdx.x] = 0;
+    if (bx == 0 && threadIdx.x < eb.mmax) eb.cnt[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_edge_plan(EdgeArgs a) { edge_plan_body(a, blockIdx.x); }
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(256) void k_edge_items(EdgeArgs a) {
+    extern __shared__ float4 lds[];
+    edge_items_body<KIND, OT, OBS>(a, lds, blockIdx.x, gridDim.x);
+}
+
+__global__ __launch_bounds__(256) void k_edge_finish(EdgeArgs a) { edge_finish_body(a, blockIdx.x); }
+
+// Many problems per launch: blockIdx.y selects the problem's record (through
+// `members` for the per-scene-class item kernel); blocks past the problem's
+// own grid leave at once.
+__global__ __launch_bounds__(256) void k_edge_plan_multi(const EdgeArgs *av) {
+    const EdgeArgs &a = av[blockIdx.y];
+    if ((int)blockIdx.x >= a.nb_edge) return;
+    edge_plan_body(a, blockIdx.x);
+}
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(256) void k_edge_items_multi(const EdgeArgs *av, const int32_t *members) {
+    extern __shared__ float4 lds[];
+    const EdgeArgs &a = av[members[blockIdx.y]];
+    if ((int)blockIdx.x >= a.nb_items) return;
+    edge_items_body<KIND, OT, OBS>(a, lds, blockIdx.x, a.nb_items);
+}
+
+__global__ __launch_bounds__(256) void k_edge_finish_multi(const EdgeArgs *av) {
+    const EdgeArgs &a = av[blockIdx.y];
+    if ((int)blockIdx.x >= a.nb_edge) return;
+    edge_finish_body(a, blockIdx.x);
 }
 
 // Obstacles held in registers per tile: 4, 8 or 16 (more obstacles run as
@@ -266,26 +303,66 @@ void edge_bufs_free(EdgeBufs &eb) {
     eb = EdgeBufs{};
 }
 
+EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
+                   const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
+                   unsigned long long *work, int min_item_blocks) {
+    EdgeArgs a;
+    a.sc = sc;
+    a.eb = eb;
+    a.xa = xa;
+    a.xb = xb;
+    a.valid = valid;
+    a.free_out = free_out;
+    a.first_hit = first_hit;
+    a.work = work;
+    a.E = E;
+    a.lpe_shift = lpe_shift;
+    a.nb_edge = (int)((E + 255) / 256);
+    // enough groups to cover the first-rank items of every edge, capped so
+    // that a grid-stride loop covers the rest
+    const int64_t per_block = 4 * (int64_t)(64 >> lpe_shift);
+    const int64_t want = (E + per_block - 1) / per_block;
+    a.nb_items = (int)std::min<int64_t>(std::max<int64_t>(want, min_item_blocks), 8192);
+    return a;
+}
+
 hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                               const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
                               hipStream_t s, unsigned long long *work) {
     if (E <= 0) return hipSuccess;
     if (E > eb.cap) return hipErrorInvalidValue;
-    const int L = 1 << lpe_shift;
-    const int eblocks = (int)((E + 255) / 256);
-    k_edge_plan<<<eblocks, 256, 0, s>>>(E, sc.d, sc.v_d, sc.h_d, L, eb.mmax, xa, xb, valid, eb);
-    // enough groups to cover the first-rank items of every edge, capped so
-    // that a grid-stride loop covers the rest
-    const int G = 64 >> lpe_shift;
-    const int64_t per_block = 4 * (int64_t)G;
-    const int64_t want = (E + per_block - 1) / per_block;
-    const int blocks = (int)(want < 8192 ? (want < 1024 ? 1024 : want) : 8192);
-    const size_t lds = scene_lds_bytes(sc);
-    dispatch_scene(sc, [&](auto kind, auto ot, auto obs) {
+    return launch_edge_args(edge_args(sc, eb, E, xa, xb, valid, free_out, first_hit, lpe_shift, work, 1024), s);
+}
+
+hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
+    if (a.E <= 0) return hipSuccess;
+    if (a.E > a.eb.cap) return hipErrorInvalidValue;
+    k_edge_plan<<<a.nb_edge, 256, 0, s>>>(a);
+    const size_t lds = scene_lds_bytes(a.sc);
+    dispatch_scene(a.sc, [&](auto kind, auto ot, auto obs) {
         k_edge_items<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
-            <<<dim3(blocks), dim3(256), lds, s>>>(sc, xa, xb, eb, lpe_shift);
+            <<<dim3(a.nb_items), dim3(256), lds, s>>>(a);
     });
-    k_edge_finish<<<eblocks, 256, 0, s>>>(E, valid, eb, free_out, first_hit, work);
+    k_edge_finish<<<a.nb_edge, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s) {
+    k_edge_plan_multi<<<dim3(max_nb_edge, P), 256, 0, s>>>(d_args);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_items_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
+                                   int n_members, int max_nb_items, size_t lds, hipStream_t s) {
+    dispatch_scene(cls, [&](auto kind, auto ot, auto obs) {
+        k_edge_items_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+            <<<dim3(max_nb_items, n_members), dim3(256), lds, s>>>(d_args, d_members);
+    });
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_finish_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s) {
+    k_edge_finish_multi<<<dim3(max_nb_edge, P), 256, 0, s>>>(d_args);
     return hipGetLastError();
 }
 

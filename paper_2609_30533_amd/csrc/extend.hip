@@ -24,6 +24,7 @@
 #include <chrono>
 #include <vector>
 
+#include "pipeline.hpp"
 #include "rng.hpp"
 #include "st_internal.hpp"
 
@@ -44,17 +45,6 @@ __device__ __forceinline__ int worker_pool(int8_t dir, int32_t grp) { return dir
 // a1: sampling
 // ---------------------------------------------------------------------------
 
-struct SampleArgs {
-    SceneDev sc;
-    WindowsDev win;
-    const PlanDev *pl;
-    int32_t variant, N;
-    float p_guided, p_new;
-    uint32_t seed, pid;
-    int64_t iter, B;
-    double t_min, t_max;  // arrival range (the learned histogram spans it)
-    st_samples out;
-};
 
 // Root time for group g of the current interval-root allocation, in double:
 // with probability p_guided (when the guided windows below Ubar are not empty)
@@ -83,9 +73,14 @@ __device__ double ir_root_time(const WindowsDev &w, const PlanDev *pl, int g, co
     return I0 + unit24d(u[3]) * (I1 - I0);
 }
 
-template <int KIND, int OT, int OBS>
-__global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
+// MULTI: many problems per launch; blockIdx.y picks the problem's record
+// (through the member list of its scene class) and blocks past the problem's
+// own grid leave at once.  The same convention holds for every kernel below.
+template <int KIND, int OT, int OBS, bool MULTI>
+__global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs *av, const int32_t *members) {
     extern __shared__ float4 lds[];
+    const SampleArgs &a = MULTI ? av[members[blockIdx.y]] : a0;
+    if (MULTI && (int)blockIdx.x >= a.nb) return;
     const SceneDev &sc = a.sc;
     const bool ir = a.variant == ST_INTERVAL_ROOT;
     if (ir) stage_obstacles(sc, lds);
@@ -218,20 +213,6 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a) {
 // bucketing of queries by node set
 // ---------------------------------------------------------------------------
 
-struct PrepArgs {
-    PlanDev *pl;
-    int32_t variant, n_pools, d;
-    int64_t B;
-    st_samples s;       // mode 0 (nearest node)
-    const int8_t *status; // mode 1 (bridges)
-    const int8_t *dir;
-    int32_t *set_of, *order;
-    int4 *tiles;
-    int32_t *n_tiles;
-    float *qbuf;        // mode 0: AoS copy of the queries
-    unsigned long long *keys;
-    int32_t mode;       // 0 nearest node, 1 bridges
-};
 
 // Adds `amount` lanes' worth to bucket[set] with one atomic per distinct set
 // in the wave; returns each lane's position among the lanes of its set (in
@@ -253,7 +234,9 @@ __device__ __forceinline__ int wave_bucket_add(int *bucket, int set) {
     return pos;
 }
 
-__global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) {
+    const PrepArgs &a = MULTI ? av[blockIdx.y] : a0;
     __shared__ int cnt[kMaxPools + 2], cur[kMaxPools + 2];
     const int tid = threadIdx.x;
     const int nsets = a.mode == 0 ? a.n_pools : 2;
@@ -328,34 +311,21 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
 
 enum { kScanRho = 0, kScanConfig = 1, kScanBridge = 2 };
 
-struct ScanArgs {
-    TreeDev tree;
-    const PlanDev *pl;
-    int32_t use_snap, variant;
-    float v;
-    const float *qbuf;      // AoS queries [.][d+1]
-    const int32_t *order;   // query ids per tile slot (null: identity)
-    const int4 *tiles;
-    const int32_t *n_tiles;
-    unsigned long long *keys;  // nearest node: per-query atomic minimum
-    unsigned long long *pkey;  // bridges: [nch][pstride]
-    int32_t *pidx;
-    int64_t pstride;
-    int32_t nch;
-};
 
 // One block = one tile of up to 256 queries (one per thread) against the
 // y-th of nch slices of its node set.  The set is a single pool or the
 // concatenation of the backward pools; nodes stream through LDS in rounds of
 // 256 (each thread loads one node, coalesced per SoA row), and the next
 // round is fetched into registers while the current one is scanned.
-template <int MODE>
-__global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a) {
+template <int MODE, bool MULTI>
+__global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av, const int32_t *members) {
     __shared__ float sx[kTileQ][8];
     __shared__ float sT[kTileQ];
     __shared__ int32_t sI[kTileQ];
     __shared__ int32_t s_pool[kMaxPools + 1], s_pre[kMaxPools + 1];
     __shared__ int32_t s_np;
+    const ScanArgs &a = MULTI ? av[members[blockIdx.z]] : a0;
+    if (MULTI && (int)blockIdx.y >= a.nch) return;
     const int t = blockIdx.x;
     if (t >= a.n_tiles[0]) return;
     const int tid = threadIdx.x;
@@ -477,23 +447,15 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a) {
 // a3: steering
 // ---------------------------------------------------------------------------
 
-struct SteerArgs {
-    SceneDev sc;
-    TreeDev tree;
-    const PlanDev *pl;
-    int32_t variant;
-    float eta;
-    int64_t B;
-    st_samples s;
-    Work w;
-};
 
-__global__ __launch_bounds__(256) void k_steer(SteerArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av) {
+    const SteerArgs &a = MULTI ? av[blockIdx.y] : a0;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.B) return;
     const SceneDev &sc = a.sc;
     const int d = sc.d, W = d + 1;
-    Work &k = a.w;
+    const Work &k = a.w;
     k.new_idx[w] = -1;
     k.parent[w] = -1;
     k.edge_valid[w] = 0;
@@ -568,24 +530,18 @@ __global__ __launch_bounds__(256) void k_steer(SteerArgs a) {
 // a5: insertion, one block per pool, workers in index order
 // ---------------------------------------------------------------------------
 
-struct InsertArgs {
-    SceneDev sc;
-    TreeDev tree;
-    PlanDev *pl;
-    int32_t variant;
-    int64_t B;
-    st_samples s;
-    Work w;
-};
 
-__global__ __launch_bounds__(1024) void k_insert(InsertArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs *av) {
     __shared__ int wsum[32];
     __shared__ int s_total, s_last;
+    const InsertArgs &a = MULTI ? av[blockIdx.y] : a0;
     const int p = blockIdx.x;
+    if (MULTI && p >= a.tree.n_pools) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int nw = blockDim.x >> 6;
     PlanDev *pl = a.pl;
-    Work &k = a.w;
+    const Work &k = a.w;
     const int d = a.tree.d, W = d + 1;
     const int64_t base = pool_base(a.tree, p);
     const int64_t snap = pl->count_snap[p];
@@ -663,20 +619,15 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a) {
 // a6: bridge selection merge
 // ---------------------------------------------------------------------------
 
-struct BridgeArgs {
-    TreeDev tree;
-    int64_t B;
-    int32_t nch;
-    const int8_t *dir;
-    Work w;
-};
 
-__global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const BridgeArgs *av) {
+    const BridgeArgs &a = MULTI ? av[blockIdx.y] : a0;
     // one wave per worker: lane y reads the y-th slice's best candidate
     const int lane = threadIdx.x & 63;
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (w >= a.B) return;
-    Work &k = a.w;
+    const Work &k = a.w;
     const int d = a.tree.d, W = d + 1;
     const bool adv = k.status[w] == ST_STATUS_ADVANCED;
     unsigned long long bk = kNoKey;
@@ -722,13 +673,6 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a) {
 // a7: incumbent publish (lexicographic (U', C', worker) minimum)
 // ---------------------------------------------------------------------------
 
-struct PublishArgs {
-    PlanDev *pl;
-    int64_t B;
-    const int8_t *dir;
-    Work w;
-    st_extend_out out;
-};
 
 __device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, float c2, int w2) {
     if (u1 != u2) return u1 < u2;
@@ -736,11 +680,13 @@ __device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, f
     return (uint32_t)w1 < (uint32_t)w2;
 }
 
-__global__ __launch_bounds__(1024) void k_publish(PublishArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishArgs *av) {
     __shared__ float sU[1024], sC[1024];
     __shared__ int sW[1024];
+    const PublishArgs &a = MULTI ? av[blockIdx.y] : a0;
     const int tid = threadIdx.x;
-    Work &k = a.w;
+    const Work &k = a.w;
     float bu = INFINITY, bc = INFINITY;
     int bw = -1;
     for (int64_t w = tid; w < a.B; w += blockDim.x) {
@@ -818,17 +764,12 @@ __global__ void k_xnew_out(XnewOutArgs a) {
 // a8 / a9: allocation update after a strict drop of U
 // ---------------------------------------------------------------------------
 
-struct RootsArgs {
-    SceneDev sc;
-    TreeDev tree;
-    WindowsDev win;
-    PlanDev *pl;
-    int32_t variant, N;
-};
 
-__global__ __launch_bounds__(256) void k_roots(RootsArgs a) {
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_roots(RootsArgs a0, const RootsArgs *av) {
     __shared__ int cand[kMaxGroups], assign[kMaxGroups], donor[kMaxGroups];
     __shared__ int s_kend;
+    const RootsArgs &a = MULTI ? av[blockIdx.y] : a0;
     PlanDev *pl = a.pl;
     if (pl->improved != 2) return;
     const int tid = threadIdx.x, N = a.N;
@@ -1054,6 +995,7 @@ void work_free(st_problem *p) {
 }
 
 static int max_tiles(int64_t B, int n_sets) { return (int)((B + kTileQ - 1) / kTileQ) + n_sets; }
+int max_query_tiles(int64_t B, int n_sets) { return max_tiles(B, n_sets); }
 
 int work_reserve(st_problem *p, int64_t B) {
     if (p->work.Bcap >= B) return ST_OK;
@@ -1103,6 +1045,7 @@ static int nch_for(int tiles) {
     int n = 1024 / std::max(tiles, 1);
     return std::max(1, std::min(kMaxNch, n));
 }
+int nch_for_tiles(int tiles) { return nch_for(tiles); }
 
 void prof_mark(st_problem *p, int stage, hipStream_t s) {
     if (!p->prof) return;
@@ -1117,9 +1060,9 @@ void prof_mark(st_problem *p, int stage, hipStream_t s) {
     p->prof_used++;
 }
 
-int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s) {
-    prof_mark(p, kStSample, s);
+SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out) {
     SampleArgs a;
+    memset(&a, 0, sizeof a);
     a.sc = p->sc;
     a.win = p->win;
     a.pl = p->d_plan;
@@ -1134,11 +1077,17 @@ int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, 
     a.t_min = p->t_min;
     a.t_max = p->t_max;
     a.out = out;
-    const int blocks = (int)((B + 255) / 256);
+    a.nb = (int)((B + 255) / 256);
+    return a;
+}
+
+int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s) {
+    prof_mark(p, kStSample, s);
+    const SampleArgs a = make_sample_args(p, iter, B, out);
     const size_t lds = scene_lds_bytes(p->sc);
     dispatch_scene2(p->sc, [&](auto kind, auto ot, auto obs) {
-        k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
-            <<<dim3(blocks), dim3(256), lds, s>>>(a);
+        k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, false>
+            <<<dim3(a.nb), dim3(256), lds, s>>>(a, nullptr, nullptr);
     });
     ST_HIP(hipGetLastError());
     return ST_OK;
@@ -1146,18 +1095,13 @@ int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, 
 
 static int edge_shift(const st_problem *p, bool bridge) { return bridge ? p->tune_br : p->tune_ext; }
 
-int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s) {
-    int rc = work_reserve(p, B);
-    if (rc != ST_OK) return rc;
-    if (p->ebufs.cap < B) {
-        graphs_free(p);
-        if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
-    }
-    Work &w = p->work;
+void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, int nch_nn,
+                    int nch_br, int min_item_blocks, IterArgs &a) {
+    const Work &w = p->work;
     const int np = p->tree.n_pools;
     const int d = p->d;
     // snapshot + buckets for the nearest-node scans (a2)
-    PrepArgs pa;
+    PrepArgs &pa = a.prep_nn;
     memset(&pa, 0, sizeof pa);
     pa.pl = p->d_plan;
     pa.variant = p->prm.variant;
@@ -1172,11 +1116,8 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     pa.qbuf = w.xb;  // AoS queries (xb is free until the bridge stage)
     pa.keys = w.nn_key;
     pa.mode = 0;
-    prof_mark(p, kStNearest, s);
-    k_prep<<<1, 1024, 0, s>>>(pa);
-    ST_HIP(hipGetLastError());
-    const int mt_nn = max_tiles(B, np);
-    ScanArgs sa;
+    a.mt_nn = max_tiles(B, np);
+    ScanArgs &sa = a.scan_nn;
     memset(&sa, 0, sizeof sa);
     sa.tree = p->tree;
     sa.pl = p->d_plan;
@@ -1188,14 +1129,9 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     sa.tiles = (const int4 *)w.tiles;
     sa.n_tiles = w.n_tiles;
     sa.keys = w.nn_key;
-    sa.nch = nch_for(mt_nn);
-    if (p->prm.variant == ST_INTERVAL_ROOT)
-        k_scan<kScanRho><<<dim3(mt_nn, sa.nch), kTileQ, 0, s>>>(sa);
-    else
-        k_scan<kScanConfig><<<dim3(mt_nn, sa.nch), kTileQ, 0, s>>>(sa);
-    ST_HIP(hipGetLastError());
+    sa.nch = nch_nn;
     // steering (a3)
-    SteerArgs ta;
+    SteerArgs &ta = a.steer;
     ta.sc = p->sc;
     ta.tree = p->tree;
     ta.pl = p->d_plan;
@@ -1204,17 +1140,11 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     ta.B = B;
     ta.s = in;
     ta.w = w;
-    const int blocks = (int)((B + 255) / 256);
-    prof_mark(p, kStSteer, s);
-    k_steer<<<blocks, 256, 0, s>>>(ta);
-    ST_HIP(hipGetLastError());
     // extension edge checks (a4)
-    prof_mark(p, kStEdge, s);
-    ST_HIP(launch_check_edges(p->sc, p->ebufs, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit,
-                              edge_shift(p, false), s, p->d_plan->work));
-    prof_mark(p, kStInsert, s);
+    a.edge_ext = edge_args(p->sc, p->ebufs, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit,
+                           edge_shift(p, false), p->d_plan->work, min_item_blocks);
     // insertion (a5)
-    InsertArgs ia;
+    InsertArgs &ia = a.insert;
     ia.sc = p->sc;
     ia.tree = p->tree;
     ia.pl = p->d_plan;
@@ -1222,63 +1152,131 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     ia.B = B;
     ia.s = in;
     ia.w = w;
-    k_insert<<<np, 1024, 0, s>>>(ia);
-    ST_HIP(hipGetLastError());
     // bridges (a6)
-    pa.mode = 1;
-    pa.status = w.status;
-    pa.dir = in.dir;
-    prof_mark(p, kStBridgeSel, s);
-    k_prep<<<1, 1024, 0, s>>>(pa);
-    ST_HIP(hipGetLastError());
-    const int mt_br = max_tiles(B, 2);
-    ScanArgs sb = sa;
+    a.prep_br = pa;
+    a.prep_br.mode = 1;
+    a.prep_br.status = w.status;
+    a.prep_br.dir = in.dir;
+    a.mt_br = max_tiles(B, 2);
+    ScanArgs &sb = a.scan_br;
+    sb = sa;
     sb.qbuf = w.xnew;
     sb.keys = nullptr;
     sb.pkey = w.br_key;
     sb.pidx = w.br_idx;
     sb.pstride = B;
-    sb.nch = nch_for(mt_br);
-    k_scan<kScanBridge><<<dim3(mt_br, sb.nch), kTileQ, 0, s>>>(sb);
-    ST_HIP(hipGetLastError());
-    BridgeArgs ba;
+    sb.nch = nch_br;
+    BridgeArgs &ba = a.merge;
     ba.tree = p->tree;
     ba.B = B;
-    ba.nch = sb.nch;
+    ba.nch = nch_br;
     ba.dir = in.dir;
     ba.w = w;
-    k_bridge_merge<<<(int)((B * 64 + 255) / 256), 256, 0, s>>>(ba);
-    ST_HIP(hipGetLastError());
-    prof_mark(p, kStBridgeEdge, s);
-    ST_HIP(launch_check_edges(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit,
-                              edge_shift(p, true), s, p->d_plan->work + 2));
-    prof_mark(p, kStPublish, s);
+    a.edge_br = edge_args(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true),
+                          p->d_plan->work + 2, min_item_blocks);
     // publish (a7)
-    PublishArgs pb;
+    PublishArgs &pb = a.publish;
     pb.pl = p->d_plan;
     pb.B = B;
     pb.dir = in.dir;
     pb.w = w;
     if (out) pb.out = *out;
     else memset(&pb.out, 0, sizeof pb.out);
-    k_publish<<<1, 1024, 0, s>>>(pb);
-    ST_HIP(hipGetLastError());
-    if (out && out->xnew) {
-        XnewOutArgs xa{B, d, w.status, w.xnew, out->xnew};
-        k_xnew_out<<<blocks, 256, 0, s>>>(xa);
-        ST_HIP(hipGetLastError());
-    }
     // allocation update (a8 / a9)
-    RootsArgs ra;
+    RootsArgs &ra = a.roots;
     ra.sc = p->sc;
     ra.tree = p->tree;
     ra.win = p->win;
     ra.pl = p->d_plan;
     ra.variant = p->prm.variant;
     ra.N = p->prm.n_groups;
-    k_roots<<<1, 256, 0, s>>>(ra);
+}
+
+int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s) {
+    int rc = work_reserve(p, B);
+    if (rc != ST_OK) return rc;
+    if (p->ebufs.cap < B) {
+        graphs_free(p);
+        if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
+    }
+    IterArgs a;
+    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools)), nch_for(max_tiles(B, 2)), 1024, a);
+    const int blocks = (int)((B + 255) / 256);
+    prof_mark(p, kStNearest, s);
+    k_prep<false><<<1, 1024, 0, s>>>(a.prep_nn, nullptr);
+    ST_HIP(hipGetLastError());
+    if (p->prm.variant == ST_INTERVAL_ROOT)
+        k_scan<kScanRho, false><<<dim3(a.mt_nn, a.scan_nn.nch), kTileQ, 0, s>>>(a.scan_nn, nullptr, nullptr);
+    else
+        k_scan<kScanConfig, false><<<dim3(a.mt_nn, a.scan_nn.nch), kTileQ, 0, s>>>(a.scan_nn, nullptr, nullptr);
+    ST_HIP(hipGetLastError());
+    prof_mark(p, kStSteer, s);
+    k_steer<false><<<blocks, 256, 0, s>>>(a.steer, nullptr);
+    ST_HIP(hipGetLastError());
+    prof_mark(p, kStEdge, s);
+    ST_HIP(launch_edge_args(a.edge_ext, s));
+    prof_mark(p, kStInsert, s);
+    k_insert<false><<<p->tree.n_pools, 1024, 0, s>>>(a.insert, nullptr);
+    ST_HIP(hipGetLastError());
+    prof_mark(p, kStBridgeSel, s);
+    k_prep<false><<<1, 1024, 0, s>>>(a.prep_br, nullptr);
+    ST_HIP(hipGetLastError());
+    k_scan<kScanBridge, false><<<dim3(a.mt_br, a.scan_br.nch), kTileQ, 0, s>>>(a.scan_br, nullptr, nullptr);
+    ST_HIP(hipGetLastError());
+    k_bridge_merge<false><<<(int)((B * 64 + 255) / 256), 256, 0, s>>>(a.merge, nullptr);
+    ST_HIP(hipGetLastError());
+    prof_mark(p, kStBridgeEdge, s);
+    ST_HIP(launch_edge_args(a.edge_br, s));
+    prof_mark(p, kStPublish, s);
+    k_publish<false><<<1, 1024, 0, s>>>(a.publish, nullptr);
+    ST_HIP(hipGetLastError());
+    if (out && out->xnew) {
+        XnewOutArgs xa{B, p->d, p->work.status, p->work.xnew, out->xnew};
+        k_xnew_out<<<blocks, 256, 0, s>>>(xa);
+        ST_HIP(hipGetLastError());
+    }
+    k_roots<false><<<1, 256, 0, s>>>(a.roots, nullptr);
     ST_HIP(hipGetLastError());
     prof_mark(p, kStEnd, s);
+    return ST_OK;
+}
+
+// ---------------------------------------------------------------------------
+// many problems per launch: one iteration of every problem of a batch
+// ---------------------------------------------------------------------------
+
+int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
+    for (const BatchClass &c : L.classes) {
+        dispatch_scene2(c.key, [&](auto kind, auto ot, auto obs) {
+            k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, true>
+                <<<dim3(c.nb_sample, c.n), dim3(256), c.lds, s>>>(SampleArgs{}, L.sample, c.members);
+        });
+    }
+    ST_HIP(hipGetLastError());
+    k_prep<true><<<dim3(1, L.P), 1024, 0, s>>>(PrepArgs{}, L.prep_nn);
+    if (L.n_ir > 0)
+        k_scan<kScanRho, true><<<dim3(L.mt_nn, L.nch, L.n_ir), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.ir_members);
+    if (L.n_rr > 0)
+        k_scan<kScanConfig, true>
+            <<<dim3(L.mt_nn, L.nch, L.n_rr), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.rr_members);
+    k_steer<true><<<dim3(L.nb_worker, L.P), 256, 0, s>>>(SteerArgs{}, L.steer);
+    ST_HIP(hipGetLastError());
+    ST_HIP(launch_edge_plan_multi(L.edge_ext, L.P, L.nb_edge, s));
+    for (const BatchClass &c : L.classes)
+        ST_HIP(launch_edge_items_multi(c.key, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));
+    ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
+    k_insert<true><<<dim3(L.max_pools, L.P), 1024, 0, s>>>(InsertArgs{}, L.insert);
+    k_prep<true><<<dim3(1, L.P), 1024, 0, s>>>(PrepArgs{}, L.prep_br);
+    k_scan<kScanBridge, true><<<dim3(L.mt_br, L.nch, L.P), kTileQ, 0, s>>>(ScanArgs{}, L.scan_br, L.all_members);
+    k_bridge_merge<true><<<dim3(L.nb_merge, L.P), 256, 0, s>>>(BridgeArgs{}, L.merge);
+    ST_HIP(hipGetLastError());
+    ST_HIP(launch_edge_plan_multi(L.edge_br, L.P, L.nb_edge, s));
+    for (const BatchClass &c : L.classes)
+        ST_HIP(launch_edge_items_multi(c.key, L.edge_br, c.members, c.n, c.nb_items_br, c.lds, s));
+    ST_HIP(launch_edge_finish_multi(L.edge_br, L.P, L.nb_edge, s));
+    k_publish<true><<<dim3(1, L.P), 1024, 0, s>>>(PublishArgs{}, L.publish);
+    k_roots<true><<<dim3(1, L.P), 256, 0, s>>>(RootsArgs{}, L.roots);
+    ST_HIP(hipGetLastError());
     return ST_OK;
 }
 
@@ -1305,8 +1303,8 @@ int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64
     sa.n_tiles = w.n_tiles;
     sa.keys = w.nn_key;
     sa.nch = nch_for(nt);
-    if (metric == ST_METRIC_RHO) k_scan<kScanRho><<<dim3(nt, sa.nch), kTileQ, 0, s>>>(sa);
-    else k_scan<kScanConfig><<<dim3(nt, sa.nch), kTileQ, 0, s>>>(sa);
+    if (metric == ST_METRIC_RHO) k_scan<kScanRho, false><<<dim3(nt, sa.nch), kTileQ, 0, s>>>(sa, nullptr, nullptr);
+    else k_scan<kScanConfig, false><<<dim3(nt, sa.nch), kTileQ, 0, s>>>(sa, nullptr, nullptr);
     ST_HIP(hipGetLastError());
     k_nn_out<<<(int)((M + 255) / 256), 256, 0, s>>>(M, metric, w.nn_key, idx_out, dist_out);
     ST_HIP(hipGetLastError());
@@ -1324,6 +1322,8 @@ static st_samples work_samples(st_problem *p) {
     s.tr = w.tr;
     return s;
 }
+
+st_samples work_samples_of(st_problem *p) { return work_samples(p); }
 
 void graphs_free(st_problem *p) {
     for (int k = 0; k < 2; ++k) {
@@ -1407,6 +1407,71 @@ static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
     return ST_OK;
 }
 
+// Start state check and the trivial case q_s = q_g (arrival at time 0 when
+// the arrival range allows it).  Synchronous.
+int start_check(st_problem *p, bool *start_free, bool *trivial) {
+    const int d = p->d, W = d + 1;
+    bool same = true;
+    for (int j = 0; j < d; ++j) same = same && p->q_s[j] == p->q_g[j];
+    float *dx = nullptr;
+    uint8_t *dfree = nullptr;
+    ST_HIP(hipMalloc((void **)&dx, W * sizeof(float)));
+    ST_HIP(hipMalloc((void **)&dfree, 1));
+    std::vector<float> xs(W);
+    for (int j = 0; j < d; ++j) xs[j] = (float)p->q_s[j];
+    xs[d] = 0.f;
+    ST_HIP(hipMemcpy(dx, xs.data(), W * sizeof(float), hipMemcpyHostToDevice));
+    ST_HIP(launch_check_states(p->sc, 1, dx, dfree, 0));
+    uint8_t f = 0;
+    ST_HIP(hipMemcpy(&f, dfree, 1, hipMemcpyDeviceToHost));
+    (void)hipFree(dx);
+    (void)hipFree(dfree);
+    *start_free = f != 0;
+    *trivial = same && f && p->L <= 0.0;
+    return ST_OK;
+}
+
+// The incumbent path (forward chain, then backward chain) into host memory.
+int fetch_path(st_problem *p, hipStream_t s, st_path *out) {
+    const int W = p->d + 1;
+    const int32_t max_n = 1 << 16;
+    float *dpath = nullptr;
+    int32_t *dn = nullptr;
+    int rc = ST_OK;
+    PlanDev host;
+    if (hipMalloc((void **)&dpath, (size_t)max_n * W * sizeof(float)) != hipSuccess ||
+        hipMalloc((void **)&dn, sizeof(int32_t)) != hipSuccess) {
+        set_error("path extraction: out of device memory");
+        rc = ST_ENOMEM;
+    } else {
+        k_path<<<1, 1, 0, s>>>(p->tree, p->d_plan, max_n, dpath, dn);
+        int32_t n = 0;
+        if (hipMemcpyAsync(&n, dn, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            set_error("path extraction: device copy failed");
+            rc = ST_EHIP;
+        } else {
+            std::vector<float> buf((size_t)std::max(n, 1) * W);
+            if (n > 0) (void)hipMemcpy(buf.data(), dpath, (size_t)n * W * sizeof(float), hipMemcpyDeviceToHost);
+            out->dof = p->d;
+            out->iterations = p->iter;
+            out->arrival = host.U;
+            out->length = host.C;
+            if (host.first_iter >= 0) out->first_solution_iter = host.first_iter;
+            if (n > 0) {
+                out->n_states = n;
+                out->states = (double *)malloc(sizeof(double) * (size_t)n * W);
+                for (size_t i = 0; i < (size_t)n * W; ++i) out->states[i] = buf[i];
+            }
+            rc = n > 0 ? ST_OK : ST_NO_SOLUTION;
+        }
+    }
+    if (dpath) (void)hipFree(dpath);
+    if (dn) (void)hipFree(dn);
+    return rc;
+}
+
 }  // namespace st
 
 using namespace st;
@@ -1487,23 +1552,10 @@ int st_plan(st_problem *p, const st_budget *b, st_path *out) {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     };
     const int d = p->d, W = d + 1;
-    // trivial case: q_s = q_g with a free start, arrival at time 0 allowed
-    bool same = true;
-    for (int j = 0; j < d; ++j) same = same && p->q_s[j] == p->q_g[j];
-    float *dx = nullptr;
-    uint8_t *dfree = nullptr;
-    ST_HIP(hipMalloc((void **)&dx, W * sizeof(float)));
-    ST_HIP(hipMalloc((void **)&dfree, 1));
-    std::vector<float> xs(W);
-    for (int j = 0; j < d; ++j) xs[j] = (float)p->q_s[j];
-    xs[d] = 0.f;
-    ST_HIP(hipMemcpy(dx, xs.data(), W * sizeof(float), hipMemcpyHostToDevice));
-    ST_HIP(launch_check_states(p->sc, 1, dx, dfree, 0));
-    uint8_t start_free = 0;
-    ST_HIP(hipMemcpy(&start_free, dfree, 1, hipMemcpyDeviceToHost));
-    (void)hipFree(dx);
-    (void)hipFree(dfree);
-    if (same && start_free && p->L <= 0.0) {
+    bool start_free = false, trivial = false;
+    int rc0 = start_check(p, &start_free, &trivial);
+    if (rc0 != ST_OK) return rc0;
+    if (trivial) {
         out->n_states = 1;
         out->states = (double *)malloc(sizeof(double) * W);
         for (int j = 0; j < d; ++j) out->states[j] = p->q_s[j];
@@ -1545,35 +1597,7 @@ int st_plan(st_problem *p, const st_budget *b, st_path *out) {
         if (b->max_ms > 0 && ms_since() >= b->max_ms) break;
         if (b->max_iters <= 0 && b->max_ms <= 0 && !b->stop_at_first) break;
     }
-    if (rc == ST_OK) {
-        const int32_t max_n = 1 << 16;
-        float *dpath = nullptr;
-        int32_t *dn = nullptr;
-        if (hipMalloc((void **)&dpath, (size_t)max_n * W * sizeof(float)) != hipSuccess ||
-            hipMalloc((void **)&dn, sizeof(int32_t)) != hipSuccess) {
-            set_error("st_plan: out of device memory");
-            rc = ST_ENOMEM;
-        } else {
-            k_path<<<1, 1, 0, s>>>(p->tree, p->d_plan, max_n, dpath, dn);
-            int32_t n = 0;
-            (void)hipMemcpyAsync(&n, dn, sizeof n, hipMemcpyDeviceToHost, s);
-            (void)hipMemcpyAsync(host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s);
-            (void)hipStreamSynchronize(s);
-            std::vector<float> buf((size_t)std::max(n, 1) * W);
-            if (n > 0) (void)hipMemcpy(buf.data(), dpath, (size_t)n * W * sizeof(float), hipMemcpyDeviceToHost);
-            out->iterations = p->iter;
-            out->arrival = host->U;
-            out->length = host->C;
-            if (n > 0) {
-                out->n_states = n;
-                out->states = (double *)malloc(sizeof(double) * (size_t)n * W);
-                for (size_t i = 0; i < (size_t)n * W; ++i) out->states[i] = buf[i];
-            }
-            rc = n > 0 ? ST_OK : ST_NO_SOLUTION;
-        }
-        if (dpath) (void)hipFree(dpath);
-        if (dn) (void)hipFree(dn);
-    }
+    if (rc == ST_OK) rc = fetch_path(p, s, out);
     (void)hipHostFree(host);
     (void)hipStreamDestroy(s);
     out->total_ms = ms_since();

@@ -1,0 +1,156 @@
+// pipeline.hpp -- launch records of the extend pipeline's kernels (one
+// record per kernel and problem) and the many-problem launch description.
+#pragma once
+
+#include <vector>
+
+#include "st_internal.hpp"
+
+namespace st {
+
+struct SampleArgs {
+    SceneDev sc;
+    WindowsDev win;
+    const PlanDev *pl;
+    int32_t variant, N;
+    float p_guided, p_new;
+    uint32_t seed, pid;
+    int64_t iter, B;
+    double t_min, t_max;  // arrival range (the learned histogram spans it)
+    st_samples out;
+    int32_t nb;           // blocks (many-problem launches)
+};
+
+struct PrepArgs {
+    PlanDev *pl;
+    int32_t variant, n_pools, d;
+    int64_t B;
+    st_samples s;       // mode 0 (nearest node)
+    const int8_t *status; // mode 1 (bridges)
+    const int8_t *dir;
+    int32_t *set_of, *order;
+    int4 *tiles;
+    int32_t *n_tiles;
+    float *qbuf;        // mode 0: AoS copy of the queries
+    unsigned long long *keys;
+    int32_t mode;       // 0 nearest node, 1 bridges
+};
+
+struct ScanArgs {
+    TreeDev tree;
+    const PlanDev *pl;
+    int32_t use_snap, variant;
+    float v;
+    const float *qbuf;      // AoS queries [.][d+1]
+    const int32_t *order;   // query ids per tile slot (null: identity)
+    const int4 *tiles;
+    const int32_t *n_tiles;
+    unsigned long long *keys;  // nearest node: per-query atomic minimum
+    unsigned long long *pkey;  // bridges: [nch][pstride]
+    int32_t *pidx;
+    int64_t pstride;
+    int32_t nch;
+};
+
+struct SteerArgs {
+    SceneDev sc;
+    TreeDev tree;
+    const PlanDev *pl;
+    int32_t variant;
+    float eta;
+    int64_t B;
+    st_samples s;
+    Work w;
+};
+
+struct InsertArgs {
+    SceneDev sc;
+    TreeDev tree;
+    PlanDev *pl;
+    int32_t variant;
+    int64_t B;
+    st_samples s;
+    Work w;
+};
+
+struct BridgeArgs {
+    TreeDev tree;
+    int64_t B;
+    int32_t nch;
+    const int8_t *dir;
+    Work w;
+};
+
+struct PublishArgs {
+    PlanDev *pl;
+    int64_t B;
+    const int8_t *dir;
+    Work w;
+    st_extend_out out;
+};
+
+struct RootsArgs {
+    SceneDev sc;
+    TreeDev tree;
+    WindowsDev win;
+    PlanDev *pl;
+    int32_t variant, N;
+};
+
+// Every record of one iteration of one problem.
+struct IterArgs {
+    PrepArgs prep_nn, prep_br;
+    ScanArgs scan_nn, scan_br;
+    SteerArgs steer;
+    EdgeArgs edge_ext, edge_br;
+    InsertArgs insert;
+    BridgeArgs merge;
+    PublishArgs publish;
+    RootsArgs roots;
+    int mt_nn, mt_br;  // query tiles at most
+};
+
+SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out);
+// nch_*: node slices per scan tile; min_item_blocks: least blocks of the edge
+// item kernel.
+void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, int nch_nn,
+                    int nch_br, int min_item_blocks, IterArgs &a);
+
+// Problems whose scene compiles to the same kernel instance (robot kind,
+// obstacle tile, obstacle-time mode).
+struct BatchClass {
+    SceneDev key;           // kind, ot and obs_mode select the instance
+    const int32_t *members; // device: record indices
+    int n;                  // members
+    int nb_sample, nb_items_ext, nb_items_br;  // grid maxima over the members
+    size_t lds;             // dynamic LDS, maximum over the members
+};
+
+// Device arrays of records (P problems) and grid maxima for one iteration of
+// every problem of a batch.
+struct BatchLaunch {
+    int P = 0;
+    const SampleArgs *sample = nullptr;
+    const PrepArgs *prep_nn = nullptr, *prep_br = nullptr;
+    const ScanArgs *scan_nn = nullptr, *scan_br = nullptr;
+    const SteerArgs *steer = nullptr;
+    const EdgeArgs *edge_ext = nullptr, *edge_br = nullptr;
+    const InsertArgs *insert = nullptr;
+    const BridgeArgs *merge = nullptr;
+    const PublishArgs *publish = nullptr;
+    const RootsArgs *roots = nullptr;
+    const int32_t *ir_members = nullptr, *rr_members = nullptr, *all_members = nullptr;
+    int n_ir = 0, n_rr = 0;
+    int mt_nn = 0, mt_br = 0, nch = 1, nb_worker = 0, nb_edge = 0, nb_merge = 0, max_pools = 0;
+    std::vector<BatchClass> classes;
+};
+
+int launch_batch_iteration(const BatchLaunch &L, hipStream_t s);
+int start_check(st_problem *p, bool *start_free, bool *trivial);
+int fetch_path(st_problem *p, hipStream_t s, st_path *out);
+st_samples work_samples_of(st_problem *p);
+size_t scene_lds_bytes(const SceneDev &sc);
+int nch_for_tiles(int tiles);
+int max_query_tiles(int64_t B, int n_sets);
+
+}  // namespace st

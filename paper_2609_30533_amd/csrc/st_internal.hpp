@@ -99,6 +99,21 @@ struct EdgeBufs {
     int32_t *cnt = nullptr;     // [16] items per rank list
 };
 
+// One edge-check launch: the edges, their buffers and the grid sizes.
+struct EdgeArgs {
+    SceneDev sc;
+    EdgeBufs eb;
+    const float *xa, *xb;       // [E][d+1]
+    const uint8_t *valid;       // [E] or null (all valid)
+    uint8_t *free_out;          // [E]
+    int32_t *first_hit;         // [E] or null
+    unsigned long long *work;   // two work counters or null
+    int64_t E;
+    int32_t lpe_shift;          // lanes per chunk = 1 << lpe_shift
+    int32_t nb_edge;            // blocks of the per-edge kernels
+    int32_t nb_items;           // blocks of the item kernel
+};
+
 // Per-batch work buffers (capacity Bcap workers).
 struct Work {
     int64_t Bcap;
@@ -181,6 +196,17 @@ void edge_bufs_free(EdgeBufs &eb);
 hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                               const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
                               hipStream_t s, unsigned long long *work = nullptr);
+// Record of one edge launch; the item kernel gets at least min_item_blocks blocks.
+EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
+                   const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
+                   unsigned long long *work, int min_item_blocks);
+hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s);
+// The same pipeline for P problems at once (records in device memory); the
+// item kernel runs once per scene class over its member records.
+hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);
+hipError_t launch_edge_items_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
+                                   int n_members, int max_nb_items, size_t lds, hipStream_t s);
+hipError_t launch_edge_finish_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);
 
 // ---- stage timing ------------------------------------------------------------
 enum Stage { kStSample = 0, kStNearest, kStSteer, kStEdge, kStInsert, kStBridgeSel, kStBridgeEdge, kStPublish,

@@ -68,6 +68,11 @@ class Path(C.Structure):
                 ("first_solution_iter", C.c_int64), ("first_solution_ms", C.c_double), ("total_ms", C.c_double)]
 
 
+class BatchResult(C.Structure):
+    _fields_ = [("first_ms", C.c_void_p), ("first_iter", C.c_void_p), ("arrival", C.c_void_p),
+                ("iterations", C.c_int64), ("total_ms", C.c_double), ("n_solved", C.c_int32)]
+
+
 class Info(C.Structure):
     _fields_ = [("U", C.c_double), ("C", C.c_double), ("inc_fwd", C.c_int64), ("inc_bwd", C.c_int64),
                 ("L", C.c_double), ("H", C.c_double), ("k_lo", C.c_int64), ("k_hi", C.c_int64),
@@ -83,8 +88,10 @@ EXPORTS = [
     "st_set_tuning", "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
     "st_mlp_create", "st_mlp_destroy", "st_mlp_param_count", "st_mlp_params", "st_mlp_grads", "st_mlp_forward",
     "st_mlp_loss", "st_mlp_backward", "st_mlp_adam", "st_proposal_set",
+    "st_path_get", "st_batch_create", "st_batch_destroy", "st_batch_iterate", "st_batch_plan",
 ]
-NO_INT_RESULT = ("st_problem_destroy", "st_path_free", "st_last_error", "st_mlp_destroy", "st_mlp_param_count")
+NO_INT_RESULT = ("st_problem_destroy", "st_path_free", "st_last_error", "st_mlp_destroy", "st_mlp_param_count",
+                 "st_batch_destroy")
 STAGES = ["sample", "nearest", "steer", "edge_check", "insert", "bridge_select", "bridge_check", "publish"]
 
 _lib = None
@@ -127,6 +134,12 @@ def load():
     L.st_work_counters.argtypes = [vp, vp]
     L.st_last_error.argtypes = []
     L.st_last_error.restype = C.c_char_p
+    L.st_path_get.argtypes = [vp, C.POINTER(Path)]
+    L.st_batch_create.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp)]
+    L.st_batch_destroy.argtypes = [vp]
+    L.st_batch_destroy.restype = None
+    L.st_batch_iterate.argtypes = [vp, i64, vp]
+    L.st_batch_plan.argtypes = [vp, C.POINTER(Budget), C.POINTER(BatchResult)]
     L.st_mlp_create.argtypes = [i32, i32, C.POINTER(vp)]
     L.st_mlp_destroy.argtypes = [vp]
     L.st_mlp_destroy.restype = None
@@ -290,6 +303,15 @@ class Problem:
         b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
         path = Path()
         rc = _check(self.L.st_plan(self.h, C.byref(b), C.byref(path)), "st_plan")
+        return self._path_dict(rc, path)
+
+    def path(self):
+        """The current incumbent path (st_path_get)."""
+        path = Path()
+        rc = _check(self.L.st_path_get(self.h, C.byref(path)), "st_path_get")
+        return self._path_dict(rc, path)
+
+    def _path_dict(self, rc, path):
         try:
             n = path.n_states
             states = np.ctypeslib.as_array(path.states, shape=(n * (self.d + 1),)).reshape(n, self.d + 1).copy() \
@@ -445,3 +467,41 @@ class Mlp:
 
 
 ST_MLP_OUTPUTS = 168
+
+
+class Batch:
+    """Many problems per launch sequence (st_batch_*).  Keeps the Problem
+    objects alive for its own lifetime."""
+
+    def __init__(self, problems, iters_per_launch=4):
+        self.L = load()
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p.h for p in self.problems])
+        h = C.c_void_p()
+        _check(self.L.st_batch_create(arr, len(self.problems), int(iters_per_launch), C.byref(h)), "st_batch_create")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.st_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def iterate(self, iters, stream=None):
+        _check(self.L.st_batch_iterate(self.h, int(iters), _stream(stream)), "st_batch_iterate")
+
+    def plan(self, max_iters=0, max_ms=0.0, stop_at_first=False, iters_per_sync=0):
+        n = len(self.problems)
+        first_ms = np.zeros(n)
+        first_iter = np.zeros(n, dtype=np.int64)
+        arrival = np.zeros(n)
+        r = BatchResult(first_ms.ctypes.data, first_iter.ctypes.data, arrival.ctypes.data, 0, 0.0, 0)
+        b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
+        _check(self.L.st_batch_plan(self.h, C.byref(b), C.byref(r)), "st_batch_plan")
+        return dict(first_ms=first_ms, first_iter=first_iter, U=arrival, iterations=r.iterations,
+                    total_ms=r.total_ms, n_solved=r.n_solved)
