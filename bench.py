@@ -9,8 +9,10 @@ update.  `value` is space-time edge checks decided per second over the timed
 steps (extension and bridge edges), with the problem resident in HBM.
 
 Printed as one JSON line; see the fields for the roofline of the dominant
-kernel, the oracle's throughput on the host cores, the stage breakdown and
-the median time to first solution.
+kernel, the oracle's throughput on the host cores, the stage breakdown, the
+median time to first solution of the plain planner (one problem at a time)
+against the learned proposal in a batch of many problems, and the
+heterogeneous batch's edge-check throughput.
 """
 from __future__ import annotations
 
@@ -77,14 +79,132 @@ def cpu_baseline(prob, seconds=12.0):
                        "FP64 single thread, %.1f s, %d edges" % (it, prob.params.batch, dt, edges))
 
 
+def eval_problem(seed, B=256, cap_fwd=1 << 16, cap_bwd=1 << 13):
+    """An evaluation problem of the 6-DOF arm workload (seeds below the
+    training and tuning ranges) with the batch's sample count and capacities."""
+    from paper_2609_30533_amd import scenes
+    p = scenes.arm6(seed)
+    p.params.batch = B
+    p.params.cap_fwd = cap_fwd
+    p.params.cap_bwd = cap_bwd
+    return p
+
+
+def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None):
+    """Plan all problems as one batch; returns the batch result and the summed
+    work counters of its members."""
+    from paper_2609_30533_amd import autotune
+    if table is not None:
+        for p in probs:
+            autotune.apply(p, table)
+    gps = [lib.Problem(p, problem_id=i) for i, p in enumerate(probs)]
+    if table is not None:
+        for p, g in zip(probs, gps):
+            autotune.apply(p, table, g)
+    if proposal is not None:
+        proposal.install(gps, probs, mix)
+    b = lib.Batch(gps)
+    w0 = [g.work_counters() for g in gps]
+    r = b.plan(max_ms=budget_ms)
+    w1 = [g.work_counters() for g in gps]
+    edges = sum((a["edges"] - z["edges"]) + (a["bridges"] - z["bridges"]) for a, z in zip(w1, w0))
+    states = sum((a["edge_states"] - z["edge_states"]) + (a["bridge_states"] - z["bridge_states"])
+                 for a, z in zip(w1, w0))
+    b.close()
+    for g in gps:
+        g.close()
+    r["edges"] = edges
+    r["states"] = states
+    return r
+
+
+def ttfs_section(lib, args):
+    """Median time to first solution: plain sampler one problem at a time
+    (the paper's setting) against the learned proposal in a batch of many
+    problems, on the same evaluation seeds."""
+    from paper_2609_30533_amd import proposal
+    P = args.ttfs_batch
+    wpath = os.path.join(ROOT, "paper_2609_30533_amd", "data", "proposal_arm6.npy")
+    prop = proposal.Proposal(proposal.load_weights(wpath), max_batch=P)
+    seeds = list(range(P))
+    plain_b = batched_run(lib, [eval_problem(s) for s in seeds], args.ttfs_ms)
+    learned_b = batched_run(lib, [eval_problem(s) for s in seeds], args.ttfs_ms, proposal=prop)
+    fp, fl = plain_b["first_ms"], learned_b["first_ms"]
+    solvable = [s for i, s in enumerate(seeds) if math.isfinite(fp[i]) or math.isfinite(fl[i])]
+    single = {}
+    for mode in ("plain", "learned"):
+        t, U = {}, {}
+        for s in solvable:
+            p = eval_problem(s, B=4096, cap_fwd=1 << 18, cap_bwd=1 << 16)
+            g = lib.Problem(p)
+            if mode == "learned":
+                prop.install([g], [p], 0.5)
+            r = g.plan(max_ms=args.ttfs_single_ms, stop_at_first=True, iters_per_sync=1)
+            if r["first_iter"] >= 0:
+                t[s], U[s] = r["first_ms"], r["U"]
+            g.close()
+        single[mode] = (t, U)
+    tp, Up = single["plain"]
+    common = [s for s in solvable if s in tp and math.isfinite(fl[s])]
+
+    def med(v):
+        return float(np.median(v)) if len(v) else None
+
+    return {
+        "ttfs_workload": "arm6 evaluation seeds 0..%d (6-DOF arm, 16 moving spheres); plain = one problem at a "
+                         "time, B=4096, %.0f ms budget; batched = all %d problems in one batch, B=256 each, "
+                         "%.0f ms budget; learned = proposal network mixed 50/50" % (
+                             P - 1, args.ttfs_single_ms, P, args.ttfs_ms),
+        "ttfs_solvable": len(solvable),
+        "ttfs_common": len(common),
+        "ttfs_ms_median_plain": med([tp[s] for s in common]),
+        "ttfs_ms_median_learned_batched": med([fl[s] for s in common]),
+        "ttfs_ms_median_plain_batched": med([fp[s] for s in common if math.isfinite(fp[s])]),
+        "ttfs_ms_median_learned_single": med([single["learned"][0][s] for s in common if s in single["learned"][0]]),
+        "arrival_mean_plain": med([]) if not common else float(np.mean([Up[s] for s in common])),
+        "arrival_mean_learned_batched": float(np.mean([learned_b["U"][s] for s in common])) if common else None,
+        "solved_plain_single": len(tp),
+        "solved_learned_single": len(single["learned"][0]),
+        "solved_plain_batched": int(plain_b["n_solved"]),
+        "solved_learned_batched": int(learned_b["n_solved"]),
+        "batched_wall_ms": float(learned_b["total_ms"]),
+        "plain_sequential_wall_ms_solvable": float(sum(tp.values()) + args.ttfs_single_ms * (len(solvable) - len(tp))),
+    }
+
+
+def batched_section(lib, args):
+    """The heterogeneous batch: 512 problems (DOF 2/6/7, 4-64 obstacles,
+    arrival widths 5-60 s, capacities 2^14-2^18) in one batch, samples per
+    problem and lanes per edge from the tuning table."""
+    from paper_2609_30533_amd import autotune, scenes
+    tpath = os.path.join(ROOT, "paper_2609_30533_amd", "data", "tuning.json")
+    table = autotune.load(tpath) if os.path.exists(tpath) else {}
+    probs = [scenes.mixed(s) for s in range(args.batch_problems)]
+    r = batched_run(lib, probs, args.batch_ms, table=table)
+    fm = r["first_ms"][np.isfinite(r["first_ms"])]
+    return {
+        "batched_workload": "mixed seeds 0..%d: DOF 2/6/7, 4-64 obstacles, arrival widths 5-60 s, tree "
+                            "capacity 2^14-2^18, one batch, %.0f ms" % (args.batch_problems - 1, args.batch_ms),
+        "batched_edge_checks_per_s": r["edges"] / (r["total_ms"] * 1e-3),
+        "batched_iterations": int(r["iterations"]),
+        "batched_solved": int(r["n_solved"]),
+        "batched_ttfs_ms_median": float(np.median(fm)) if len(fm) else None,
+        "batched_states": int(r["states"]),
+        "tuning_table": "paper_2609_30533_amd/data/tuning.json" if table else None,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--roofline-steps", type=int, default=10)
-    ap.add_argument("--ttfs-problems", type=int, default=12)
-    ap.add_argument("--ttfs-ms", type=float, default=1500.0)
+    ap.add_argument("--ttfs-batch", type=int, default=512, help="evaluation problems (0: skip the comparison)")
+    ap.add_argument("--ttfs-ms", type=float, default=2000.0, help="budget of each batched evaluation run")
+    ap.add_argument("--ttfs-single-ms", type=float, default=1000.0, help="budget of each single-problem run")
+    ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
+    ap.add_argument("--batch-ms", type=float, default=2000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
@@ -134,20 +254,8 @@ def main():
     dominant = max(stages, key=lambda k: stages[k][0])
     inf = gp.info()
 
-    # time to first solution, plain sampler, one problem at a time
-    ttfs, solved, tried = [], 0, 0
-    s = seed
-    while tried < args.ttfs_problems:
-        try:
-            s, p2, g2 = pick_problem(scenes.arm6, lib, first_seed=s + 1)
-        except RuntimeError:
-            break
-        tried += 1
-        res = g2.plan(max_ms=args.ttfs_ms, stop_at_first=True, iters_per_sync=1)
-        if res["first_iter"] >= 0:
-            solved += 1
-            ttfs.append(res["first_ms"])
-        g2.close()
+    ttfs = ttfs_section(lib, args) if args.ttfs_batch > 0 else {}
+    batched = batched_section(lib, args) if args.batch_problems > 0 else {}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,12 +289,10 @@ def main():
         "dominant_stage": dominant,
         "edges_per_step": edges / args.steps,
         "tree_nodes": int(sum(gp.export()["counts"])),
-        "ttfs_ms_median_plain": float(np.median(ttfs)) if ttfs else None,
-        "ttfs_ms_mean_plain": float(np.mean(ttfs)) if ttfs else None,
-        "ttfs_solved": solved,
-        "ttfs_problems": tried,
         "incumbent_U": inf["U"] if math.isfinite(inf["U"]) else None,
     }
+    out.update(ttfs)
+    out.update(batched)
     print(json.dumps(out))
 
 

@@ -103,9 +103,13 @@ static int batch_build(st_batch *b) {
     BatchLaunch &L = b->L;
     L.P = P;
     if (P == 0) return ST_OK;
+    // node slices per scan tile: the tiles actually used are about one per
+    // 256 workers plus a partial one per node set, far fewer than the bound;
+    // aim at a few thousand scan blocks in total, at least 8 slices each so
+    // that a member's large tree is never scanned by a single block
     int64_t tiles = 0;
-    for (st_problem *p : b->mem) tiles += max_query_tiles(p->prm.batch, p->tree.n_pools);
-    const int nch = nch_for_tiles((int)std::min<int64_t>(tiles, 1 << 30));
+    for (st_problem *p : b->mem) tiles += (p->prm.batch + 255) / 256 + 2;
+    const int nch = (int)std::min<int64_t>(64, std::max<int64_t>(8, 8192 / std::max<int64_t>(tiles, 1)));
     const int min_items = std::max(1, 1024 / P);
     std::vector<SampleArgs> smp(P);
     std::vector<PrepArgs> prep_nn(P), prep_br(P);
@@ -309,6 +313,8 @@ int st_batch_plan(st_batch *b, const st_budget *budget, st_batch_result *res) {
     int64_t launches = 0;
     hipStream_t s = nullptr;
     if (P > 0) {
+        // work the caller queued on other streams (state import, proposal) comes first
+        ST_HIP(hipDeviceSynchronize());
         ST_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         if (b->ev.empty()) {
             hipEvent_t e;

@@ -1569,6 +1569,8 @@ int st_plan(st_problem *p, const st_budget *b, st_path *out) {
         out->total_ms = ms_since();
         return ST_NO_SOLUTION;
     }
+    // work the caller queued on other streams (state import, proposal) comes first
+    ST_HIP(hipDeviceSynchronize());
     hipStream_t s = nullptr;
     ST_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     PlanDev *host = nullptr;

@@ -43,7 +43,8 @@ def harvest_problem(seed: int) -> scenes.Problem:
 def harvest(n_paths: int, per_batch: int = 128, max_ms: float = 2500.0, seed0: int = TRAIN_SEED0,
             log=print, time_limit_s: float = 1e9):
     """Plan batches of training problems until n_paths solution paths exist.
-    Returns a list of (problem, path states [n, d+1])."""
+    Returns a list of (problem, path) with path a dict holding the states
+    [n, d+1], arrival U and length C."""
     out = []
     seed = seed0
     t0 = time.time()
@@ -58,7 +59,7 @@ def harvest(n_paths: int, per_batch: int = 128, max_ms: float = 2500.0, seed0: i
                 continue
             path = gp.path()
             if path["rc"] == 0 and path["states"] is not None and len(path["states"]) >= 2:
-                out.append((p, path["states"]))
+                out.append((p, path))
         b.close()
         for gp in gps:
             gp.close()
@@ -67,7 +68,7 @@ def harvest(n_paths: int, per_batch: int = 128, max_ms: float = 2500.0, seed0: i
 
 
 def make_dataset(pairs, o_max=O_MAX, k=K_STATES):
-    """Feature and target arrays for a list of (problem, path)."""
+    """Feature and target arrays for a list of (problem, path dict)."""
     M = len(pairs)
     core = np.zeros((M, scenes.PROP_CORE), dtype=np.float32)
     obs = np.zeros((M, o_max, scenes.PROP_ENC_IN), dtype=np.float32)
@@ -79,7 +80,7 @@ def make_dataset(pairs, o_max=O_MAX, k=K_STATES):
     for i, (p, path) in enumerate(pairs):
         c, o, m = scenes.proposal_features(p, o_max)
         core[i], obs[i], mask[i] = c, o, m
-        yy, ym, dm, ub = scenes.proposal_targets(p, path, k)
+        yy, ym, dm, ub = scenes.proposal_targets(p, path["states"], k)
         y[i], ymask[i], dmask[i], ubin[i] = yy, ym, dm, ub
     return dict(core=core, obs=obs, mask=mask, y=y, ymask=ymask, dmask=dmask, ubin=ubin)
 
