@@ -194,6 +194,43 @@ def batched_section(lib, args):
     }
 
 
+def edge_sweep(lib, scenes, n_edges, reps=5):
+    """st_check_edges on n_edges synthetic speed-feasible edges of the 6-DOF
+    arm problem (lengths up to 4 eta) for each obstacle tile and lane count:
+    the edge-check kernel with the whole device to itself.  Algorithmic work
+    is the states up to the first hit (all n+1 for a free edge)."""
+    import torch
+    prob = scenes.arm6(1)
+    xa, xb = scenes.synthetic_edges(prob, n_edges, seed=5, bridge_mix=True)
+    # state counts n = max(1, ceil(max(D, v dt) / h)) of the edges, host side
+    D = np.sqrt(((xb[:, :-1].astype(np.float64) - xa[:, :-1]) ** 2).sum(axis=1))
+    span = np.maximum(D, prob.v_max * np.abs(xb[:, -1].astype(np.float64) - xa[:, -1]))
+    n = np.maximum(1, np.ceil(span / prob.params.h)).astype(np.int64)
+    da, db = torch.from_numpy(xa).cuda(), torch.from_numpy(xb).cuda()
+    gp = lib.Problem(prob)
+    W = flops_per_state(prob)
+    out = []
+    for ot in (8, 16):
+        for lanes in (16, 32, 64):
+            gp.set_tuning(obstacle_tile=ot, lanes_check=lanes)
+            free, fh = gp.check_edges(da, db)
+            torch.cuda.synchronize()
+            fh = fh.cpu().numpy()
+            states = int(np.where(fh < 0, n + 1, fh + 1).sum())
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(reps):
+                gp.check_edges(da, db)
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1) / reps
+            tf = states * W / (ms * 1e-3) / 1e12
+            out.append(dict(obstacle_tile=ot, lanes=lanes, ms=ms, states=states, edges=n_edges,
+                            tflops=tf, frac=tf / PEAK_FP32_TFLOPS))
+    gp.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,6 +243,8 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--edge-sweep", type=int, default=0,
+                    help="only time st_check_edges on this many synthetic edges per launch shape and print JSON")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -217,6 +256,11 @@ def main():
     from paper_2609_30533_amd import lib, scenes
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.init()
+
+    if args.edge_sweep > 0:
+        for r in edge_sweep(lib, scenes, args.edge_sweep):
+            print(json.dumps(r), flush=True)
+        return
 
     seed, prob, gp = pick_problem(scenes.arm6, lib)
     W = flops_per_state(prob)

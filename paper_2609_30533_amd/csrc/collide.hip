@@ -51,6 +51,8 @@ __global__ __launch_bounds__(256) void k_check_states(SceneDev sc, int64_t M, co
 // ---------------------------------------------------------------------------
 
 constexpr int32_t kNoHit = 0x7fffffff;
+constexpr int kMaxItems = 16;   // work items per edge at most
+constexpr int kCntStride = 32;  // ints between rank counters (128 bytes)
 
 __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     const EdgeBufs &eb = a.eb;
@@ -79,16 +81,33 @@ __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     } else if (e < a.E) {
         eb.n[e] = -1;
     }
-    for (int r = 0; r < mmax; ++r) {
-        const bool want = m > r;
-        const uint64_t mask = __ballot(want);
-        if (mask == 0) break;
-        const int leader = __builtin_ctzll(mask);
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&eb.cnt[r], __popcll(mask));
-        base = __shfl(base, leader, 64);
-        if (want) {
-            const int slot = base + __popcll(mask & ((1ull << lane) - 1ull));
+    // rank lists: positions within the block from LDS counters (one per wave
+    // and rank), then one global atomic per rank and block; every rank's
+    // global counter sits on its own cache line
+    __shared__ int wcnt[4][kMaxItems], bbase[kMaxItems];
+    const int wave = threadIdx.x >> 6;
+    uint64_t masks[kMaxItems];
+#pragma unroll
+    for (int r = 0; r < kMaxItems; ++r) {
+        masks[r] = r < mmax ? __ballot(m > r) : 0ull;
+        if (lane == 0) wcnt[wave][r] = __popcll(masks[r]);
+    }
+    __syncthreads();
+    if (threadIdx.x < mmax) {
+        const int r = threadIdx.x;
+        int tot = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+            const int c = wcnt[w][r];
+            wcnt[w][r] = tot;
+            tot += c;
+        }
+        bbase[r] = tot > 0 ? atomicAdd(&eb.cnt[r * kCntStride], tot) : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kMaxItems; ++r) {
+        if (m > r) {
+            const int slot = bbase[r] + wcnt[wave][r] + __popcll(masks[r] & ((1ull << lane) - 1ull));
             eb.items[(int64_t)r * eb.cap + slot] = make_int2((int)e, r);
         }
     }
@@ -103,7 +122,7 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     stage_obstacles(sc, lds);
     int32_t pre[17];
     pre[0] = 0;
-    for (int r = 0; r < eb.mmax; ++r) pre[r + 1] = pre[r] + eb.cnt[r];
+    for (int r = 0; r < eb.mmax; ++r) pre[r + 1] = pre[r] + eb.cnt[r * kCntStride];
     const int64_t total = pre[eb.mmax];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpe_shift = a.lpe_shift;
@@ -196,7 +215,7 @@ __device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
         }
     }
     // the rank lists are consumed: leave them empty for the next launch
-    if (bx == 0 && threadIdx.x < eb.mmax) eb.cnt[threadIdx.x] = 0;
+    if (bx == 0 && threadIdx.x < eb.mmax) eb.cnt[threadIdx.x * kCntStride] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_edge_plan(EdgeArgs a) { edge_plan_body(a, blockIdx.x); }
@@ -291,8 +310,8 @@ int edge_bufs_reserve(EdgeBufs &eb, int64_t E) {
     ST_HIP(hipMalloc((void **)&eb.n, cap * sizeof(int32_t)));
     ST_HIP(hipMalloc((void **)&eb.hit, cap * sizeof(int32_t)));
     ST_HIP(hipMalloc((void **)&eb.items, (size_t)cap * eb.mmax * sizeof(int2)));
-    ST_HIP(hipMalloc((void **)&eb.cnt, 16 * sizeof(int32_t)));
-    ST_HIP(hipMemset(eb.cnt, 0, 16 * sizeof(int32_t)));
+    ST_HIP(hipMalloc((void **)&eb.cnt, kMaxItems * kCntStride * sizeof(int32_t)));
+    ST_HIP(hipMemset(eb.cnt, 0, kMaxItems * kCntStride * sizeof(int32_t)));
     return ST_OK;
 }
 

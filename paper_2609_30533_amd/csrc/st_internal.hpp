@@ -96,7 +96,7 @@ struct EdgeBufs {
     int32_t *n = nullptr;       // [cap] state count, -1 for skipped edges
     int32_t *hit = nullptr;     // [cap] least colliding state index found
     int2 *items = nullptr;      // [mmax][cap] (edge, rank)
-    int32_t *cnt = nullptr;     // [16] items per rank list
+    int32_t *cnt = nullptr;     // items per rank list, rank r at [32 r]
 };
 
 // One edge-check launch: the edges, their buffers and the grid sizes.

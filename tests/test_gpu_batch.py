@@ -42,9 +42,18 @@ def _members():
 
 
 def _state(gp):
+    """Used node slots of every pool (unused slots hold whatever the device
+    memory held) and the planner info."""
     st = gp.export()
     inf = gp.info()
-    return st, inf
+    p = gp.prob.params
+    used = []
+    for k, c in enumerate(st["counts"]):
+        base = 0 if k == 0 else p.cap_fwd + (k - 1) * p.cap_bwd
+        used.append(np.arange(base, base + int(c)))
+    idx = np.concatenate(used) if used else np.zeros(0, dtype=np.int64)
+    return {"counts": st["counts"], "x": st["x"][idx], "parent": st["parent"][idx], "cost": st["cost"][idx],
+            "rootT": st["rootT"][idx]}, inf
 
 
 def test_batch_equals_single_runs(oracle_lib):
