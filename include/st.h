@@ -360,6 +360,16 @@ int st_proposal_set(st_problem *p, const float *z, float mix, void *stream);
 int st_set_tuning(st_problem *p, int32_t obstacle_tile, int32_t lanes_extension, int32_t lanes_bridge,
                   int32_t lanes_check);
 
+/* Lanes per space-time state in the edge checks of the arm robots (1, 2 or 4:
+ * the state's spheres are shared out among that many lanes, each composing
+ * the kinematic chain itself; shorter dependent chains for launches too small
+ * to fill the device, more instructions per state) for extension edges,
+ * bridge edges and st_check_edges; -1 chooses by launch size (4 up to 256
+ * edges, else 1; a batch counts the edges of all its members); 0 keeps.  A translating robot always uses
+ * one lane per state.  Results do not depend on these.  Synchronous; drops
+ * captured iteration graphs. */
+int st_set_state_split(st_problem *p, int32_t split_extension, int32_t split_bridge, int32_t split_check);
+
 /* ---- measurement ---------------------------------------------------------- */
 
 #define ST_PROFILE_STAGES 9

@@ -233,7 +233,8 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.lds_sph = sc.O_pad * nseg * 2;
     sc.lds_r2 = sc.lds_sph + S;
     sc.lds_t = sc.lds_r2 + (S * sc.O_pad + 3) / 4;
-    sc.lds_f4 = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));
+    sc.lds_goal = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));
+    sc.lds_f4 = sc.lds_goal + S;
     int rc;
     if ((rc = dev_upload(&p->d_sph, sph.data(), sph.size())) != ST_OK) return rc;
     if ((rc = dev_upload(&p->d_R2, R2.data(), R2.size())) != ST_OK) return rc;
@@ -243,6 +244,12 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.R2 = p->d_R2;
     sc.seg = p->d_seg;
     sc.seg_t = p->d_segt;
+    // sphere centres at q_g for the goal-state tests
+    ST_HIP(hipMalloc((void **)&p->d_goal, std::max(S, 1) * sizeof(float4)));
+    sc.goal = nullptr;
+    ST_HIP(launch_goal_centers(sc, p->d_goal));
+    ST_HIP(hipDeviceSynchronize());
+    sc.goal = p->d_goal;
     if (scene_lds_bytes(sc) > 64 * 1024) return fail(ST_EINVAL, "obstacle table too large for LDS");
     return ST_OK;
 }
@@ -417,7 +424,7 @@ static void destroy(st_problem *p) {
     edge_bufs_free(p->ebufs);
     edge_bufs_free(p->ebufs_api);
     for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
+    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
                     p->tree.x, p->tree.parent, p->tree.cost, p->tree.rootT, p->d_plan};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -517,6 +524,29 @@ int st_set_tuning(st_problem *p, int32_t obstacle_tile, int32_t lanes_extension,
     return ST_OK;
 }
 
+int st_set_state_split(st_problem *p, int32_t split_extension, int32_t split_bridge, int32_t split_check) {
+    if (!p) return fail(ST_EINVAL, "null problem");
+    auto shift_of = [](int32_t v, int *out) {
+        switch (v) {
+            case 0: return true;
+            case -1: *out = -1; return true;
+            case 1: *out = 0; return true;
+            case 2: *out = 1; return true;
+            case 4: *out = 2; return true;
+            default: return false;
+        }
+    };
+    int se = p->split_ext, sb = p->split_br, sk = p->split_api;
+    if (!shift_of(split_extension, &se) || !shift_of(split_bridge, &sb) || !shift_of(split_check, &sk))
+        return fail(ST_EINVAL, "state split must be 1, 2 or 4, -1 (by launch size) or 0 (keep)");
+    p->split_ext = se;
+    p->split_br = sb;
+    p->split_api = sk;
+    ST_HIP(hipDeviceSynchronize());
+    graphs_free(p);
+    return ST_OK;
+}
+
 int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out, void *stream) {
     if (!p || M < 0 || (M > 0 && (!x || !free_out))) return fail(ST_EINVAL, "st_check_states: bad arguments");
     ST_HIP(launch_check_states(p->sc, M, x, free_out, (hipStream_t)stream));
@@ -531,7 +561,7 @@ int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, u
     int rc = edge_bufs_reserve(p->ebufs_api, E);
     if (rc != ST_OK) return rc;
     ST_HIP(launch_check_edges(p->sc, p->ebufs_api, E, xa, xb, nullptr, free_out, first_hit, p->tune_api,
-                              (hipStream_t)stream));
+                              (hipStream_t)stream, nullptr, split_for(p->split_api, E)));
     return ST_OK;
 }
 

@@ -111,6 +111,8 @@ static int batch_build(st_batch *b) {
     for (st_problem *p : b->mem) tiles += (p->prm.batch + 255) / 256 + 2;
     const int nch = (int)std::min<int64_t>(64, std::max<int64_t>(8, 8192 / std::max<int64_t>(tiles, 1)));
     const int min_items = std::max(1, 1024 / P);
+    int64_t all_edges = 0;
+    for (st_problem *p : b->mem) all_edges += p->prm.batch;
     std::vector<SampleArgs> smp(P);
     std::vector<PrepArgs> prep_nn(P), prep_br(P);
     std::vector<ScanArgs> scan_nn(P), scan_br(P);
@@ -121,7 +123,7 @@ static int batch_build(st_batch *b) {
     std::vector<PublishArgs> pub(P);
     std::vector<RootsArgs> roots(P);
     std::vector<int32_t> all, ir, rr;
-    std::map<std::tuple<int, int, int>, std::vector<int32_t>> cls;
+    std::map<std::tuple<int, int, int, int, int>, std::vector<int32_t>> cls;
     std::vector<PlanDev *> pls(P);
     L.nch = nch;
     for (int m = 0; m < P; ++m) {
@@ -130,7 +132,7 @@ static int batch_build(st_batch *b) {
         const st_samples s = work_samples_of(p);
         smp[m] = make_sample_args(p, -1, B, s);
         IterArgs a;
-        make_iter_args(p, B, s, nullptr, nch, nch, min_items, a);
+        make_iter_args(p, B, s, nullptr, nch, nch, min_items, all_edges, a);
         prep_nn[m] = a.prep_nn;
         prep_br[m] = a.prep_br;
         scan_nn[m] = a.scan_nn;
@@ -145,7 +147,8 @@ static int batch_build(st_batch *b) {
         pls[m] = p->d_plan;
         all.push_back(m);
         (p->prm.variant == ST_INTERVAL_ROOT ? ir : rr).push_back(m);
-        cls[std::make_tuple(p->sc.kind, p->sc.ot, p->sc.obs_mode)].push_back(m);
+        cls[std::make_tuple(p->sc.kind, p->sc.ot, p->sc.obs_mode, a.edge_ext.split_shift, a.edge_br.split_shift)]
+            .push_back(m);
         L.mt_nn = std::max(L.mt_nn, a.mt_nn);
         L.mt_br = std::max(L.mt_br, a.mt_br);
         L.nb_worker = std::max<int>(L.nb_worker, (int)((B + 255) / 256));
@@ -177,6 +180,8 @@ static int batch_build(st_batch *b) {
         memset(&c, 0, sizeof c);
         const st_problem *p0 = b->mem[kv.second[0]];
         c.key = p0->sc;
+        c.split_ext = std::get<3>(kv.first);
+        c.split_br = std::get<4>(kv.first);
         c.n = (int)kv.second.size();
         for (int32_t m : kv.second) {
             c.nb_sample = std::max(c.nb_sample, smp[m].nb);

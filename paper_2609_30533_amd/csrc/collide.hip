@@ -32,6 +32,33 @@ __global__ __launch_bounds__(256) void k_check_states(SceneDev sc, int64_t M, co
     }
 }
 
+// World centres of the robot's spheres at q_g (one thread per sphere, the
+// same kinematics code as the state tests, so the goal-state tests decide
+// exactly as a state test at q = q_g would).
+__global__ void k_goal_centers(SceneDev sc, float4 *out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= sc.S) return;
+    float q[kMaxDof];
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j) q[j] = sc.q_g[j];
+    float cx, cy, cz, as;
+    if (sc.kind == kTranslate) {
+        sphere_translate(sc, q, sc.sph[s], cx, cy, cz, as);
+    } else {
+        Frame f;
+        frame_identity(f);
+        for (int l = 1; l <= sc.d && sc.link_first[l] <= s; ++l) dh_compose(sc, l - 1, q[l - 1], f);
+        sphere_world(f, sc.sph[s], cx, cy, cz, as);
+    }
+    out[s] = make_float4(cx, cy, cz, as);
+}
+
+hipError_t launch_goal_centers(const SceneDev &sc, float4 *out) {
+    if (sc.S <= 0) return hipSuccess;
+    k_goal_centers<<<(sc.S + 63) / 64, 64>>>(sc, out);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Edge checks as a three-kernel pipeline.
 //
@@ -56,7 +83,8 @@ constexpr int kCntStride = 32;  // ints between rank counters (128 bytes)
 
 __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     const EdgeBufs &eb = a.eb;
-    const int d = a.sc.d, L = 1 << a.lpe_shift, mmax = eb.mmax;
+    // states per chunk: lanes per chunk over lanes per state
+    const int d = a.sc.d, L = 1 << (a.lpe_shift - a.split_shift), mmax = eb.mmax;
     const double v = a.sc.v_d, h = a.sc.h_d;
     const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -113,7 +141,7 @@ __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     }
 }
 
-template <int KIND, int OT, int OBS>
+template <int KIND, int OT, int OBS, int SPLIT>
 __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, int bx, int nbx) {
     const SceneDev &sc = a.sc;
     const EdgeBufs &eb = a.eb;
@@ -129,9 +157,11 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     const int lpe = 1 << lpe_shift;
     const int G = 64 >> lpe_shift;
     const int sub = lane & (lpe - 1), gsel = lane >> lpe_shift;
+    // SPLIT lanes per state: states per chunk ls, the lane's state slot and part
+    const int ls = lpe / SPLIT, slot = sub / SPLIT, part = sub & (SPLIT - 1);
     const uint64_t gbits = lpe == 64 ? ~0ull : ((1ull << lpe) - 1ull);
     const uint64_t group_mask = gbits << (gsel * lpe);
-    const uint64_t lower_mask = group_mask & ((1ull << lane) - 1ull);
+    const uint64_t lower_mask = group_mask & ((1ull << (lane & ~(SPLIT - 1))) - 1ull);
     const int w = sc.d + 1;
     const int64_t stride = (int64_t)nbx * (blockDim.x >> 6) * G;
     for (int64_t base = ((int64_t)bx * (blockDim.x >> 6) + wave) * G; base < total; base += stride) {
@@ -152,16 +182,16 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
             B = xb + (int64_t)e * w;
             if (A[sc.d] > B[sc.d]) { const float *tmp = A; A = B; B = tmp; }
             n = eb.n[e];
-            c_e = (n + lpe) / lpe;
+            c_e = (n + ls) / ls;
             m = c_e < eb.mmax ? c_e : eb.mmax;
         }
         const float inv_n = 1.0f / (float)n;
         for (int64_t c = rank;; c += m) {
             if (!done) {
                 if (c >= c_e) done = true;
-                else if (__atomic_load_n(&eb.hit[e], __ATOMIC_RELAXED) < c * lpe) done = true;
+                else if (__atomic_load_n(&eb.hit[e], __ATOMIC_RELAXED) < c * ls) done = true;
             }
-            const int64_t j = c * lpe + sub;
+            const int64_t j = c * ls + slot;
             const bool act = !done && j <= n;
             float q[kMaxDof];
             float t = 0.f;
@@ -179,10 +209,10 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
 #pragma unroll
                 for (int k = 0; k < kMaxDof; ++k) q[k] = 0.f;
             }
-            const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, q, t, act, group_mask, lower_mask);
+            const bool hit = state_hits<KIND, OT, OBS, true, SPLIT>(sc, lds, q, t, act, group_mask, lower_mask, part);
             const uint64_t hm = __ballot(hit && act) & group_mask;
             if (!done && hm) {
-                atomicMin(&eb.hit[e], (int32_t)(c * lpe + (__builtin_ctzll(hm) - gsel * lpe)));
+                atomicMin(&eb.hit[e], (int32_t)(c * ls + ((__builtin_ctzll(hm) - gsel * lpe) / SPLIT)));
                 done = true;
             }
             if (__ballot(!done) == 0) break;
@@ -220,10 +250,10 @@ __device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
 
 __global__ __launch_bounds__(256) void k_edge_plan(EdgeArgs a) { edge_plan_body(a, blockIdx.x); }
 
-template <int KIND, int OT, int OBS>
+template <int KIND, int OT, int OBS, int SPLIT>
 __global__ __launch_bounds__(256) void k_edge_items(EdgeArgs a) {
     extern __shared__ float4 lds[];
-    edge_items_body<KIND, OT, OBS>(a, lds, blockIdx.x, gridDim.x);
+    edge_items_body<KIND, OT, OBS, SPLIT>(a, lds, blockIdx.x, gridDim.x);
 }
 
 __global__ __launch_bounds__(256) void k_edge_finish(EdgeArgs a) { edge_finish_body(a, blockIdx.x); }
@@ -237,12 +267,12 @@ __global__ __launch_bounds__(256) void k_edge_plan_multi(const EdgeArgs *av) {
     edge_plan_body(a, blockIdx.x);
 }
 
-template <int KIND, int OT, int OBS>
+template <int KIND, int OT, int OBS, int SPLIT>
 __global__ __launch_bounds__(256) void k_edge_items_multi(const EdgeArgs *av, const int32_t *members) {
     extern __shared__ float4 lds[];
     const EdgeArgs &a = av[members[blockIdx.y]];
     if ((int)blockIdx.x >= a.nb_items) return;
-    edge_items_body<KIND, OT, OBS>(a, lds, blockIdx.x, a.nb_items);
+    edge_items_body<KIND, OT, OBS, SPLIT>(a, lds, blockIdx.x, a.nb_items);
 }
 
 __global__ __launch_bounds__(256) void k_edge_finish_multi(const EdgeArgs *av) {
@@ -279,6 +309,23 @@ static void dispatch_scene(const SceneDev &sc, F &&f) {
     };
     if (sc.kind == kTranslate) by_obs(IC<kTranslate>{});
     else by_obs(IC<kDH>{});
+}
+
+// f(IC<KIND>, IC<OT>, IC<OBS>, IC<SPLIT>): the lane split of a state applies
+// to the arm kind only (a translating robot has too few spheres to share).
+template <class F>
+static void dispatch_split(const SceneDev &sc, int split_shift, F &&f) {
+    dispatch_scene(sc, [&](auto kind, auto ot, auto obs) {
+        if (decltype(kind)::value == kTranslate) {
+            f(kind, ot, obs, IC<1>{});
+        } else {
+            switch (split_shift) {
+                case 1: f(kind, ot, obs, IC<2>{}); break;
+                case 2: f(kind, ot, obs, IC<4>{}); break;
+                default: f(kind, ot, obs, IC<1>{}); break;
+            }
+        }
+    });
 }
 
 size_t scene_lds_bytes(const SceneDev &sc) { return (size_t)sc.lds_f4 * sizeof(float4); }
@@ -324,8 +371,10 @@ void edge_bufs_free(EdgeBufs &eb) {
 
 EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                    const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
-                   unsigned long long *work, int min_item_blocks) {
+                   unsigned long long *work, int min_item_blocks, int split_shift) {
     EdgeArgs a;
+    // a translating robot checks one state per lane; a split never exceeds the chunk
+    a.split_shift = sc.kind == kTranslate ? 0 : std::max(0, std::min(std::min(split_shift, 2), lpe_shift));
     a.sc = sc;
     a.eb = eb;
     a.xa = xa;
@@ -347,10 +396,11 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
 
 hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                               const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
-                              hipStream_t s, unsigned long long *work) {
+                              hipStream_t s, unsigned long long *work, int split_shift) {
     if (E <= 0) return hipSuccess;
     if (E > eb.cap) return hipErrorInvalidValue;
-    return launch_edge_args(edge_args(sc, eb, E, xa, xb, valid, free_out, first_hit, lpe_shift, work, 1024), s);
+    return launch_edge_args(edge_args(sc, eb, E, xa, xb, valid, free_out, first_hit, lpe_shift, work, 1024,
+                                      split_shift), s);
 }
 
 hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
@@ -358,8 +408,8 @@ hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
     if (a.E > a.eb.cap) return hipErrorInvalidValue;
     k_edge_plan<<<a.nb_edge, 256, 0, s>>>(a);
     const size_t lds = scene_lds_bytes(a.sc);
-    dispatch_scene(a.sc, [&](auto kind, auto ot, auto obs) {
-        k_edge_items<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+    dispatch_split(a.sc, a.split_shift, [&](auto kind, auto ot, auto obs, auto split) {
+        k_edge_items<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, decltype(split)::value>
             <<<dim3(a.nb_items), dim3(256), lds, s>>>(a);
     });
     k_edge_finish<<<a.nb_edge, 256, 0, s>>>(a);
@@ -371,10 +421,11 @@ hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge
     return hipGetLastError();
 }
 
-hipError_t launch_edge_items_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
-                                   int n_members, int max_nb_items, size_t lds, hipStream_t s) {
-    dispatch_scene(cls, [&](auto kind, auto ot, auto obs) {
-        k_edge_items_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+hipError_t launch_edge_items_multi(const SceneDev &cls, int split_shift, const EdgeArgs *d_args,
+                                   const int32_t *d_members, int n_members, int max_nb_items, size_t lds,
+                                   hipStream_t s) {
+    dispatch_split(cls, split_shift, [&](auto kind, auto ot, auto obs, auto split) {
+        k_edge_items_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, decltype(split)::value>
             <<<dim3(max_nb_items, n_members), dim3(256), lds, s>>>(d_args, d_members);
     });
     return hipGetLastError();

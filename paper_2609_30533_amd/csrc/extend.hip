@@ -76,6 +76,11 @@ __device__ double ir_root_time(const WindowsDev &w, const PlanDev *pl, int g, co
 // MULTI: many problems per launch; blockIdx.y picks the problem's record
 // (through the member list of its scene class) and blocks past the problem's
 // own grid leave at once.  The same convention holds for every kernel below.
+// Lanes per worker in the sampler: the arm's root check (q_g, T) shares the
+// spheres out among four lanes; every lane of a worker draws the same numbers.
+template <int KIND>
+constexpr int sample_lanes() { return KIND == kDH ? 4 : 1; }
+
 template <int KIND, int OT, int OBS, bool MULTI>
 __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs *av, const int32_t *members) {
     extern __shared__ float4 lds[];
@@ -84,8 +89,10 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
     const SceneDev &sc = a.sc;
     const bool ir = a.variant == ST_INTERVAL_ROOT;
     if (ir) stage_obstacles(sc, lds);
-    const int lane = threadIdx.x & 63;
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int SL = sample_lanes<KIND>();
+    const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = gt / SL;
+    const int part = (int)(gt % SL);
     const bool act = w < a.B;
     const PlanDev *pl = a.pl;
     // a negative iteration means "the planner's own counter" (graph replays)
@@ -172,10 +179,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
     }
     if (ir) {
         // the proposed root (q_g, T) is checked at its own time
-        float qg[kMaxDof];
-#pragma unroll
-        for (int j = 0; j < kMaxDof; ++j) qg[j] = sc.q_g[j];
-        const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, qg, T, check_root, 1ull << lane, 0ull);
+        const bool hit = goal_hits<OT, OBS, SL>(sc, lds, T, check_root, part);
         if (check_root) {
             if (hit) flags |= ST_FLAG_SKIP;
             // Eq. 6: t_r ~ U[D(q_s, q_r)/v, T - D(q_r, q_g)/v], empty interval rejected
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
             if (dir == 1 && (!(pl->minRootT[g] < pl->U) || unit24f(u[12]) <= a.p_new)) flags |= ST_FLAG_USE_NEW;
         }
     }
-    if (!act) return;
+    if (!act || part != 0) return;
     a.out.dir[w] = dir;
     a.out.flags[w] = flags;
     a.out.grp[w] = g;
@@ -1077,7 +1081,7 @@ SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const 
     a.t_min = p->t_min;
     a.t_max = p->t_max;
     a.out = out;
-    a.nb = (int)((B + 255) / 256);
+    a.nb = (int)((B * (p->sc.kind == kDH ? sample_lanes<kDH>() : 1) + 255) / 256);
     return a;
 }
 
@@ -1096,7 +1100,7 @@ int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, 
 static int edge_shift(const st_problem *p, bool bridge) { return bridge ? p->tune_br : p->tune_ext; }
 
 void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, int nch_nn,
-                    int nch_br, int min_item_blocks, IterArgs &a) {
+                    int nch_br, int min_item_blocks, int64_t launch_edges, IterArgs &a) {
     const Work &w = p->work;
     const int np = p->tree.n_pools;
     const int d = p->d;
@@ -1142,7 +1146,8 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ta.w = w;
     // extension edge checks (a4)
     a.edge_ext = edge_args(p->sc, p->ebufs, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit,
-                           edge_shift(p, false), p->d_plan->work, min_item_blocks);
+                           edge_shift(p, false), p->d_plan->work, min_item_blocks,
+                           split_for(p->split_ext, launch_edges));
     // insertion (a5)
     InsertArgs &ia = a.insert;
     ia.sc = p->sc;
@@ -1173,7 +1178,7 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ba.dir = in.dir;
     ba.w = w;
     a.edge_br = edge_args(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true),
-                          p->d_plan->work + 2, min_item_blocks);
+                          p->d_plan->work + 2, min_item_blocks, split_for(p->split_br, launch_edges));
     // publish (a7)
     PublishArgs &pb = a.publish;
     pb.pl = p->d_plan;
@@ -1200,7 +1205,7 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
         if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
     }
     IterArgs a;
-    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools)), nch_for(max_tiles(B, 2)), 1024, a);
+    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools)), nch_for(max_tiles(B, 2)), 1024, B, a);
     const int blocks = (int)((B + 255) / 256);
     prof_mark(p, kStNearest, s);
     k_prep<false><<<1, 1024, 0, s>>>(a.prep_nn, nullptr);
@@ -1263,7 +1268,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     ST_HIP(hipGetLastError());
     ST_HIP(launch_edge_plan_multi(L.edge_ext, L.P, L.nb_edge, s));
     for (const BatchClass &c : L.classes)
-        ST_HIP(launch_edge_items_multi(c.key, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));
+        ST_HIP(launch_edge_items_multi(c.key, c.split_ext, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));
     ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
     k_insert<true><<<dim3(L.max_pools, L.P), 1024, 0, s>>>(InsertArgs{}, L.insert);
     k_prep<true><<<dim3(1, L.P), 1024, 0, s>>>(PrepArgs{}, L.prep_br);
@@ -1272,7 +1277,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     ST_HIP(hipGetLastError());
     ST_HIP(launch_edge_plan_multi(L.edge_br, L.P, L.nb_edge, s));
     for (const BatchClass &c : L.classes)
-        ST_HIP(launch_edge_items_multi(c.key, L.edge_br, c.members, c.n, c.nb_items_br, c.lds, s));
+        ST_HIP(launch_edge_items_multi(c.key, c.split_br, L.edge_br, c.members, c.n, c.nb_items_br, c.lds, s));
     ST_HIP(launch_edge_finish_multi(L.edge_br, L.P, L.nb_edge, s));
     k_publish<true><<<dim3(1, L.P), 1024, 0, s>>>(PublishArgs{}, L.publish);
     k_roots<true><<<dim3(1, L.P), 256, 0, s>>>(RootsArgs{}, L.roots);

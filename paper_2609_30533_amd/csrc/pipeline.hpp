@@ -112,14 +112,16 @@ struct IterArgs {
 
 SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out);
 // nch_*: node slices per scan tile; min_item_blocks: least blocks of the edge
-// item kernel.
+// item kernel; launch_edges: edges of the whole launch (for the automatic
+// lanes per state).
 void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, int nch_nn,
-                    int nch_br, int min_item_blocks, IterArgs &a);
+                    int nch_br, int min_item_blocks, int64_t launch_edges, IterArgs &a);
 
-// Problems whose scene compiles to the same kernel instance (robot kind,
-// obstacle tile, obstacle-time mode).
+// Problems whose scene compiles to the same kernel instances (robot kind,
+// obstacle tile, obstacle-time mode, lanes per state).
 struct BatchClass {
     SceneDev key;           // kind, ot and obs_mode select the instance
+    int split_ext, split_br;  // lanes per state (log2) of the two edge launches
     const int32_t *members; // device: record indices
     int n;                  // members
     int nb_sample, nb_items_ext, nb_items_br;  // grid maxima over the members

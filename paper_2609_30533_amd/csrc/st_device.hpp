@@ -42,7 +42,9 @@ struct SceneDev {
     float q_lo[8], q_hi[8], q_s[8], q_g[8];
     float dh_a[8], dh_ca[8], dh_sa[8], dh_d[8], dh_t0[8];
     int link_first[9];          // spheres of link l are [link_first[l], link_first[l+1])
+    int lds_goal;               // float4 offset in LDS of the sphere centres at q_g
     const float4 *sph;          // [S]
+    const float4 *goal;         // [S] world centres at q_g (x, y, z, |c|^2)
     const float *R2;            // [S][O_pad]
     const float4 *seg;          // [O_pad][n_seg][2]
     const float *seg_t;         // shared mode: [n_seg+1]; generic: [O_pad][n_seg+1]
@@ -61,7 +63,57 @@ __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds)
         const int m = sc.O_pad * (sc.n_seg + 1);
         for (int i = threadIdx.x; i < m; i += blockDim.x) lt[i] = sc.seg_t[i];
     }
+    if (sc.goal)
+        for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_goal + i] = sc.goal[i];
     __syncthreads();
+}
+
+// World frame of a link of the chain: rotation (row-major) and origin.
+struct Frame {
+    float R00, R01, R02, R10, R11, R12, R20, R21, R22, p0, p1, p2;
+};
+
+__device__ __forceinline__ void frame_identity(Frame &f) {
+    f.R00 = 1.f; f.R01 = 0.f; f.R02 = 0.f;
+    f.R10 = 0.f; f.R11 = 1.f; f.R12 = 0.f;
+    f.R20 = 0.f; f.R21 = 0.f; f.R22 = 1.f;
+    f.p0 = 0.f; f.p1 = 0.f; f.p2 = 0.f;
+}
+
+// T <- T * Rz(theta_j + q_j) Tz(d_j) Tx(a_j) Rx(alpha_j) (standard DH, joint j).
+__device__ __forceinline__ void dh_compose(const SceneDev &sc, int j, float qj, Frame &f) {
+    float st_, ct;
+    __sincosf(qj + sc.dh_t0[j], &st_, &ct);
+    const float ca = sc.dh_ca[j], sa = sc.dh_sa[j];
+    const float a = sc.dh_a[j], dd = sc.dh_d[j];
+    float u, w;
+    u = fmaf(f.R00, ct, f.R01 * st_); w = fmaf(f.R01, ct, -f.R00 * st_);
+    f.p0 = fmaf(a, u, fmaf(dd, f.R02, f.p0));
+    f.R00 = u; f.R01 = fmaf(ca, w, sa * f.R02); f.R02 = fmaf(ca, f.R02, -sa * w);
+    u = fmaf(f.R10, ct, f.R11 * st_); w = fmaf(f.R11, ct, -f.R10 * st_);
+    f.p1 = fmaf(a, u, fmaf(dd, f.R12, f.p1));
+    f.R10 = u; f.R11 = fmaf(ca, w, sa * f.R12); f.R12 = fmaf(ca, f.R12, -sa * w);
+    u = fmaf(f.R20, ct, f.R21 * st_); w = fmaf(f.R21, ct, -f.R20 * st_);
+    f.p2 = fmaf(a, u, fmaf(dd, f.R22, f.p2));
+    f.R20 = u; f.R21 = fmaf(ca, w, sa * f.R22); f.R22 = fmaf(ca, f.R22, -sa * w);
+}
+
+// World centre of a sphere given in its link frame, and |c|^2.
+__device__ __forceinline__ void sphere_world(const Frame &f, float4 sp, float &cx, float &cy, float &cz, float &as) {
+    cx = fmaf(f.R00, sp.x, fmaf(f.R01, sp.y, fmaf(f.R02, sp.z, f.p0)));
+    cy = fmaf(f.R10, sp.x, fmaf(f.R11, sp.y, fmaf(f.R12, sp.z, f.p1)));
+    cz = fmaf(f.R20, sp.x, fmaf(f.R21, sp.y, fmaf(f.R22, sp.z, f.p2)));
+    as = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
+}
+
+// Translating robot: centre = (q0, q1, q2 or 0) + offset, and |c|^2.
+__device__ __forceinline__ void sphere_translate(const SceneDev &sc, const float *q, float4 sp, float &cx, float &cy,
+                                                 float &cz, float &as) {
+    const float pz = sc.d >= 3 ? q[2] : 0.0f;
+    cx = q[0] + sp.x;
+    cy = q[1] + sp.y;
+    cz = pz + sp.z;
+    as = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
 }
 
 // Segment index for time t with waypoint times shared by all obstacles:
@@ -124,16 +176,37 @@ __device__ __forceinline__ uint64_t pair_hits(const float4 *lds, const SceneDev 
     return m;
 }
 
+// Hit of the lane's state from the lane's accumulated pair masks.  A lane
+// knows its own bit exactly (its own ballots included it); with SPLIT > 1
+// the lanes of a state ran different numbers of sphere iterations, so their
+// own bits are exchanged by one more ballot of the whole wave.  Every lane of
+// the wave must call this.
+template <int SPLIT>
+__device__ __forceinline__ bool state_hit(uint64_t hm, int st_lane) {
+    if (SPLIT == 1) return (hm >> lane_id()) & 1ull;
+    const uint64_t own = __ballot(((hm >> lane_id()) & 1ull) != 0);
+    return ((own >> st_lane) & ((1ull << SPLIT) - 1ull)) != 0;
+}
+
 // Does the lane's state (q, t) collide?  OT obstacles are held in registers
-// per tile.  `alive` enters true for lanes that must check; after every link
-// the wave ballots the hits and each lane decides whether it may stop:
-//   FIRST:  stop on an own hit, or when a lower lane of its group has hit
-//           (so the least colliding index of a group is exact);
+// per tile.  With SPLIT > 1 a state occupies SPLIT adjacent lanes (aligned)
+// and lane `part` of them tests the spheres s with s = part (mod SPLIT);
+// every lane composes the kinematic chain itself, and a state's hit is the OR
+// over its lanes, so all SPLIT lanes return the same answer.  This divides
+// the dependent chain of one state check by about SPLIT for launches too
+// small to fill the device.  `alive` enters true for lanes that must check;
+// after every link the wave ballots the hits and each lane decides whether it
+// may stop:
+//   FIRST:  stop on a hit of its state, or when a lower state of its group
+//           has hit (so the least colliding index of a group is exact);
+//           lower_mask holds the lanes of the lower states;
 //   !FIRST: stop as soon as any lane of its group has hit.
 // Every lane of the wave must call this (it contains ballots).
-template <int KIND, int OT, int OBS, bool FIRST>
+template <int KIND, int OT, int OBS, bool FIRST, int SPLIT = 1>
 __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds, const float *q, float t, bool alive,
-                                           uint64_t group_mask, uint64_t lower_mask) {
+                                           uint64_t group_mask, uint64_t lower_mask, int part = 0) {
+    static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4 || SPLIT == 8, "state split");
+    const int st_lane = lane_id() & ~(SPLIT - 1);  // first lane of this state
     bool hit = false;
     uint64_t hm = 0;  // wave mask of lanes with a colliding pair
     // configuration box and horizon
@@ -164,60 +237,89 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
             }
         }
         if (KIND == kTranslate) {
-            const float px = q[0], py = q[1], pz = sc.d >= 3 ? q[2] : 0.0f;
-            for (int s = 0; s < sc.S; ++s) {
+            for (int s = part; s < sc.S; s += SPLIT) {
                 if (alive) {
-                    const float4 sp = lds[sc.lds_sph + s];
-                    const float cx = px + sp.x, cy = py + sp.y, cz = pz + sp.z;
-                    const float as = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
+                    float cx, cy, cz, as;
+                    sphere_translate(sc, q, lds[sc.lds_sph + s], cx, cy, cz, as);
                     hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
                 }
             }
-            hit = hit || ((hm >> lane_id()) & 1ull);
+            hit = hit || state_hit<SPLIT>(hm, st_lane);
             const uint64_t m = __ballot(hit);
             if (FIRST) alive = alive && !hit && !(m & lower_mask);
             else alive = alive && !(m & group_mask);
         } else {
-            // world <- link frame: rotation R (row-major) and origin p
-            float R00 = 1.f, R01 = 0.f, R02 = 0.f, R10 = 0.f, R11 = 1.f, R12 = 0.f, R20 = 0.f, R21 = 0.f, R22 = 1.f;
-            float p0 = 0.f, p1 = 0.f, p2 = 0.f;
+            // world <- link frame
+            Frame f;
+            frame_identity(f);
 #pragma unroll
             for (int l = 0; l <= kMaxDof; ++l) {
                 if (l > sc.d) break;
-                if (l > 0 && alive) {
-                    // T <- T * Rz(theta) Tz(d) Tx(a) Rx(alpha)
-                    float st_, ct;
-                    __sincosf(q[l - 1] + sc.dh_t0[l - 1], &st_, &ct);
-                    const float ca = sc.dh_ca[l - 1], sa = sc.dh_sa[l - 1];
-                    const float a = sc.dh_a[l - 1], dd = sc.dh_d[l - 1];
-                    float u, w;
-                    u = fmaf(R00, ct, R01 * st_); w = fmaf(R01, ct, -R00 * st_);
-                    p0 = fmaf(a, u, fmaf(dd, R02, p0));
-                    R00 = u; R01 = fmaf(ca, w, sa * R02); R02 = fmaf(ca, R02, -sa * w);
-                    u = fmaf(R10, ct, R11 * st_); w = fmaf(R11, ct, -R10 * st_);
-                    p1 = fmaf(a, u, fmaf(dd, R12, p1));
-                    R10 = u; R11 = fmaf(ca, w, sa * R12); R12 = fmaf(ca, R12, -sa * w);
-                    u = fmaf(R20, ct, R21 * st_); w = fmaf(R21, ct, -R20 * st_);
-                    p2 = fmaf(a, u, fmaf(dd, R22, p2));
-                    R20 = u; R21 = fmaf(ca, w, sa * R22); R22 = fmaf(ca, R22, -sa * w);
-                }
+                if (l > 0 && alive) dh_compose(sc, l - 1, q[l - 1], f);
                 const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
                 if (s1 > s0 && __ballot(alive) != 0) {
-                    for (int s = s0; s < s1; ++s) {
+                    // this lane's spheres of the link: s = part (mod SPLIT)
+                    for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
                         if (alive) {
-                            const float4 sp = lds[sc.lds_sph + s];
-                            const float cx = fmaf(R00, sp.x, fmaf(R01, sp.y, fmaf(R02, sp.z, p0)));
-                            const float cy = fmaf(R10, sp.x, fmaf(R11, sp.y, fmaf(R12, sp.z, p1)));
-                            const float cz = fmaf(R20, sp.x, fmaf(R21, sp.y, fmaf(R22, sp.z, p2)));
-                            const float as = fmaf(cx, cx, fmaf(cy, cy, cz * cz));
+                            float cx, cy, cz, as;
+                            sphere_world(f, lds[sc.lds_sph + s], cx, cy, cz, as);
                             hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
                         }
                     }
-                    hit = hit || ((hm >> lane_id()) & 1ull);
+                    hit = hit || state_hit<SPLIT>(hm, st_lane);
                     const uint64_t m = __ballot(hit);
                     if (FIRST) alive = alive && !hit && !(m & lower_mask);
                     else alive = alive && !(m & group_mask);
                 }
+            }
+        }
+    }
+    return hit;
+}
+
+// Does (q_g, t) collide?  The same decision as state_hits at q = q_g, with
+// the sphere centres at q_g read from LDS (they are computed once per
+// problem by the same kinematics code), so only the obstacle positions at t
+// and the pair tests remain.  SPLIT lanes share a state as in state_hits;
+// lanes are independent otherwise (`alive` false: nothing to check).
+template <int OT, int OBS, int SPLIT>
+__device__ __forceinline__ bool goal_hits(const SceneDev &sc, const float4 *lds, float t, bool alive, int part) {
+    const int st_lane = lane_id() & ~(SPLIT - 1);
+    bool hit = false;
+    uint64_t hm = 0;
+    if (alive) {
+        bool out = !(t >= 0.0f) || !(t <= sc.H);
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j)
+            if (j < sc.d) out = out || !(sc.q_g[j] >= sc.q_lo[j]) || !(sc.q_g[j] <= sc.q_hi[j]);
+        hit = out;
+    }
+    alive = alive && !hit;
+    int kseg = 0;
+    if (OBS == kObsShared) kseg = shared_segment(sc, t);
+    for (int tile = 0; tile < sc.O_pad; tile += OT) {
+        if (__ballot(alive) == 0) break;
+        float nx[OT], ny[OT], nz[OT], bo[OT];
+        if (alive) {
+#pragma unroll
+            for (int i = 0; i < OT; ++i) {
+                const int o = tile + i;
+                const int k = (OBS == kObsShared) ? kseg : generic_segment(sc, lds, o, t);
+                obstacle_n(lds, sc.n_seg, o, k, t, nx[i], ny[i], nz[i]);
+                bo[i] = 0.25f * fmaf(nx[i], nx[i], fmaf(ny[i], ny[i], nz[i] * nz[i]));
+            }
+        }
+        for (int l = 0; l <= sc.d; ++l) {
+            const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
+            if (s1 > s0 && __ballot(alive) != 0) {
+                for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
+                    if (alive) {
+                        const float4 c = lds[sc.lds_goal + s];
+                        hm |= pair_hits<OT>(lds, sc, s, tile, c.x, c.y, c.z, c.w, nx, ny, nz, bo);
+                    }
+                }
+                hit = hit || state_hit<SPLIT>(hm, st_lane);
+                alive = alive && !hit;
             }
         }
     }

@@ -110,6 +110,7 @@ struct EdgeArgs {
     unsigned long long *work;   // two work counters or null
     int64_t E;
     int32_t lpe_shift;          // lanes per chunk = 1 << lpe_shift
+    int32_t split_shift;        // lanes per state = 1 << split_shift
     int32_t nb_edge;            // blocks of the per-edge kernels
     int32_t nb_items;           // blocks of the item kernel
 };
@@ -155,6 +156,7 @@ struct st_problem {
     float4 *d_sph = nullptr;
     float *d_R2 = nullptr;
     float4 *d_seg = nullptr;
+    float4 *d_goal = nullptr;  // sphere centres at q_g
     float *d_segt = nullptr;
     // goal grid and windows
     int64_t k_lo = 0, k_hi = -1;
@@ -175,6 +177,8 @@ struct st_problem {
     bool use_graphs = true;
     // lanes per edge chunk (log2) for extension, bridge and st_check_edges launches
     int tune_ext = 5, tune_br = 6, tune_api = 5;
+    // lanes per state (log2) for the same three launches; -1 chooses by size
+    int split_ext = -1, split_br = -1, split_api = -1;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int64_t graph_B = 0;
     hipStream_t cap_stream = nullptr;
@@ -189,23 +193,32 @@ namespace st {
 
 // ---- collision ------------------------------------------------------------
 size_t scene_lds_bytes(const SceneDev &sc);
+// World centres (x, y, z, |c|^2) of the robot's spheres at q_g.
+hipError_t launch_goal_centers(const SceneDev &sc, float4 *out);
 hipError_t launch_check_states(const SceneDev &sc, int64_t M, const float *x, uint8_t *free_out, hipStream_t s);
 int edge_bufs_reserve(EdgeBufs &eb, int64_t E);
 void edge_bufs_free(EdgeBufs &eb);
 // Lanes per chunk = 1 << lpe_shift (1..64).  first_hit and work may be null.
 hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                               const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
-                              hipStream_t s, unsigned long long *work = nullptr);
+                              hipStream_t s, unsigned long long *work = nullptr, int split_shift = 0);
+// Lanes per state (log2) for a launch of E edges: explicit, or by size (only
+// a few hundred edges leave most SIMDs idle, where shorter chains pay).
+inline int split_for(int setting, int64_t E) {
+    if (setting >= 0) return setting;
+    return E <= 256 ? 2 : 0;
+}
 // Record of one edge launch; the item kernel gets at least min_item_blocks blocks.
 EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                    const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
-                   unsigned long long *work, int min_item_blocks);
+                   unsigned long long *work, int min_item_blocks, int split_shift);
 hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s);
 // The same pipeline for P problems at once (records in device memory); the
 // item kernel runs once per scene class over its member records.
 hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);
-hipError_t launch_edge_items_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
-                                   int n_members, int max_nb_items, size_t lds, hipStream_t s);
+hipError_t launch_edge_items_multi(const SceneDev &cls, int split_shift, const EdgeArgs *d_args,
+                                   const int32_t *d_members, int n_members, int max_nb_items, size_t lds,
+                                   hipStream_t s);
 hipError_t launch_edge_finish_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);
 
 // ---- stage timing ------------------------------------------------------------

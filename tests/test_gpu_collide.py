@@ -78,6 +78,35 @@ def test_edges_reversed_endpoints_identical(oracle_lib):
     assert np.array_equal(h1.cpu().numpy(), h2.cpu().numpy())
 
 
+@pytest.mark.parametrize("maker", [lambda: scenes.arm6(3), lambda: scenes.arm7rr(2)], ids=["arm6", "arm7rr"])
+def test_launch_shapes_do_not_change_results(oracle_lib, maker):
+    """Obstacle tile, lanes per chunk and lanes per state change the schedule
+    only: free flags and least colliding indices are identical, and agree
+    with the oracle wherever it does not exempt the decision."""
+    from paper_2609_30533_amd.lib import Problem
+    prob = maker()
+    banner("launch shapes %s" % prob.name)
+    xa, xb = scenes.synthetic_edges(prob, 3000, seed=11, bridge_mix=True)
+    gp = Problem(prob)
+    da, db = to_dev(xa), to_dev(xb)
+    ref = None
+    for ot in (8, 16):
+        for lanes in (16, 32, 64):
+            for split in (1, 2, 4):
+                gp.set_tuning(obstacle_tile=ot, lanes_check=lanes)
+                gp.set_state_split(check=split)
+                f, h = gp.check_edges(da, db)
+                cur = (f.cpu().numpy(), h.cpu().numpy())
+                if ref is None:
+                    ref = cur
+                    continue
+                assert np.array_equal(cur[0], ref[0]), (ot, lanes, split)
+                assert np.array_equal(cur[1], ref[1]), (ot, lanes, split)
+    res = oracle_lib.Oracle(prob).check_edges(xa, xb)
+    ok = ~_exempt(res)
+    assert np.array_equal(ref[0][ok].astype(bool), res["free"][ok].astype(bool))
+
+
 def test_edges_degenerate_and_long(oracle_lib):
     """Zero-length edges, pure waits, edges leaving the box or the horizon,
     and long bridges that span thousands of states."""
