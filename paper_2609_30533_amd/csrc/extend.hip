@@ -245,38 +245,63 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
     const int tid = threadIdx.x;
     const int nsets = a.mode == 0 ? a.n_pools : 2;
     for (int i = tid; i < nsets; i += blockDim.x) cnt[i] = 0;
-    if (a.mode == 0 && tid == 0) {
-        // the snapshot every worker of this batch sees
-        for (int i = 0; i < a.n_pools; ++i) a.pl->count_snap[i] = a.pl->count[i];
-        a.pl->U_snap = a.pl->U;
-        a.pl->improved = 0;
+    if (a.mode == 0) {
+        // the snapshot every worker of this batch sees (one pool per thread:
+        // a serial copy would wait for every load in turn)
+        if (tid < a.n_pools) a.pl->count_snap[tid] = a.pl->count[tid];
+        if (tid == 0) {
+            const float U = a.pl->U;
+            a.pl->U_snap = U;
+            a.pl->improved = 0;
+        }
     }
     __syncthreads();
-    for (int64_t base = 0; base < a.B; base += blockDim.x) {
-        const int64_t w = base + tid;
-        int set = -1;
-        if (w < a.B) {
+    // R consecutive workers per thread and pass, all loads before the stores
+    constexpr int R = 4;
+    const bool one_pass = a.B <= (int64_t)blockDim.x * R;
+    int sets[R];
+    for (int64_t base = 0; base < a.B; base += (int64_t)blockDim.x * R) {
+        uint8_t f[R];
+        int8_t dr[R];
+        int32_t g[R];
+        int8_t stt[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t w = base + (int64_t)tid * R + r;
+            const bool in = w < a.B;
             if (a.mode == 0) {
-                const uint8_t f = a.s.flags[w];
-                const int8_t dir = a.s.dir[w];
-                const int32_t g = a.s.grp[w];
-                if (!(f & ST_FLAG_SKIP)) {
-                    if (dir == 0) set = 0;
-                    else if (g >= 0 && g < a.n_pools - 1 &&
-                             !(a.variant == ST_INTERVAL_ROOT && (f & ST_FLAG_USE_NEW)))
-                        set = 1 + g;
+                f[r] = in ? a.s.flags[w] : ST_FLAG_SKIP;
+                dr[r] = in ? a.s.dir[w] : 0;
+                g[r] = in ? a.s.grp[w] : -1;
+            } else {
+                stt[r] = in ? a.status[w] : 0;
+                dr[r] = in ? a.dir[w] : 0;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t w = base + (int64_t)tid * R + r;
+            int set = -1;
+            if (a.mode == 0) {
+                if (!(f[r] & ST_FLAG_SKIP)) {
+                    if (dr[r] == 0) set = 0;
+                    else if (g[r] >= 0 && g[r] < a.n_pools - 1 &&
+                             !(a.variant == ST_INTERVAL_ROOT && (f[r] & ST_FLAG_USE_NEW)))
+                        set = 1 + g[r];
                 }
-                for (int j = 0; j < a.d; ++j) a.qbuf[w * (a.d + 1) + j] = a.s.qr[(int64_t)j * a.B + w];
-                a.qbuf[w * (a.d + 1) + a.d] = a.s.tr[w];
-                a.keys[w] = kNoKey;
             } else {
                 // forward new nodes bridge into the backward forest (set 0), backward
                 // new nodes into the forward tree (set 1)
-                if (a.status[w] == ST_STATUS_ADVANCED) set = a.dir[w] == 0 ? 0 : 1;
+                if (stt[r] == ST_STATUS_ADVANCED) set = dr[r] == 0 ? 0 : 1;
             }
-            a.set_of[w] = set;
+            if (w < a.B) {
+                a.set_of[w] = set;
+                if (a.mode == 0) a.keys[w] = kNoKey;
+            }
+            sets[r] = w < a.B ? set : -1;
         }
-        wave_bucket_add(cnt, set);
+#pragma unroll
+        for (int r = 0; r < R; ++r) wave_bucket_add(cnt, sets[r]);
     }
     __syncthreads();
     if (tid == 0) {
@@ -301,11 +326,21 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
         a.n_tiles[0] = t;
     }
     __syncthreads();
-    for (int64_t base = 0; base < a.B; base += blockDim.x) {
-        const int64_t w = base + tid;
-        const int set = w < a.B ? a.set_of[w] : -1;
-        const int pos = wave_bucket_add(cur, set);
-        if (set >= 0) a.order[pos] = (int32_t)w;
+    if (one_pass) {
+        // the sets are still in registers
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t w = (int64_t)tid * R + r;
+            const int pos = wave_bucket_add(cur, sets[r]);
+            if (sets[r] >= 0) a.order[pos] = (int32_t)w;
+        }
+    } else {
+        for (int64_t base = 0; base < a.B; base += blockDim.x) {
+            const int64_t w = base + tid;
+            const int set = w < a.B ? a.set_of[w] : -1;
+            const int pos = wave_bucket_add(cur, set);
+            if (set >= 0) a.order[pos] = (int32_t)w;
+        }
     }
 }
 
@@ -326,7 +361,7 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     __shared__ float sx[kTileQ][8];
     __shared__ float sT[kTileQ];
     __shared__ int32_t sI[kTileQ];
-    __shared__ int32_t s_pool[kMaxPools + 1], s_pre[kMaxPools + 1];
+    __shared__ int32_t s_pool[kMaxPools + 1], s_pre[kMaxPools + 1], s_cnt[kMaxPools + 1];
     __shared__ int32_t s_np;
     const ScanArgs &a = MULTI ? av[members[blockIdx.z]] : a0;
     if (MULTI && (int)blockIdx.y >= a.nch) return;
@@ -339,13 +374,19 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     const int d = a.tree.d;
     const PlanDev *pl = a.pl;
     const float U = a.use_snap ? pl->U_snap : pl->U;
+    // pools of the set and their prefix sums: the counts are loaded by one
+    // thread per pool, the prefix is formed from LDS
+    const int p_lo = set >= 0 ? set : 1, p_hi = set >= 0 ? set + 1 : a.tree.n_pools;
+    for (int p = p_lo + tid; p < p_hi; p += blockDim.x) {
+        int c = a.use_snap ? pl->count_snap[p] : pl->count[p];
+        if (a.variant == ST_ROOT_RECYCLING && set < 0 && !pl->slot_active[p - 1]) c = 0;
+        s_cnt[p - p_lo] = c;
+    }
+    __syncthreads();
     if (tid == 0) {
-        // pools of the set and their prefix sums
         int k = 0, acc = 0;
-        const int p_lo = set >= 0 ? set : 1, p_hi = set >= 0 ? set + 1 : a.tree.n_pools;
         for (int p = p_lo; p < p_hi; ++p) {
-            if (a.variant == ST_ROOT_RECYCLING && set < 0 && !pl->slot_active[p - 1]) continue;
-            const int c = a.use_snap ? pl->count_snap[p] : pl->count[p];
+            const int c = s_cnt[p - p_lo];
             if (c <= 0) continue;
             s_pool[k] = p;
             s_pre[k] = acc;
@@ -364,8 +405,8 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     float qx[kMaxDof];
     float aq = 0.f;
 #pragma unroll
-    for (int j = 0; j < kMaxDof; ++j) qx[j] = (act && j < d) ? a.qbuf[(int64_t)q * (d + 1) + j] : 0.f;
-    if (act) aq = sv * a.qbuf[(int64_t)q * (d + 1) + d];
+    for (int j = 0; j < kMaxDof; ++j) qx[j] = (act && j < d) ? a.qx[(int64_t)q * a.sq + (int64_t)j * a.sj] : 0.f;
+    if (act) aq = sv * a.qt[(int64_t)q * a.st];
     float best = INFINITY, bestT = INFINITY;
     int32_t bi = -1;
     const float *X = a.tree.x;
@@ -520,14 +561,17 @@ __global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av
         xnew[d] = xn[d] + sigma * step / sc.v;  // Eq. 8: maximum-speed timing
     }
     if (!(xnew[d] >= 0.f && xnew[d] <= sc.H)) return;  // leaves [0, H]
+    // loads before the stores (which may alias them for the compiler)
+    const float cost0 = virt ? 0.f : a.tree.cost[idx];
+    const float root0 = dir == 0 ? 0.f : (virt ? a.s.T[w] : a.tree.rootT[idx]);
     for (int j = 0; j <= d; ++j) {
         k.xn[w * W + j] = xn[j];
         k.xnew[w * W + j] = xnew[j];
     }
     k.edge_valid[w] = 1;
     k.parent[w] = idx;
-    k.cost_new[w] = (virt ? 0.f : a.tree.cost[idx]) + step;
-    k.rootT_new[w] = dir == 0 ? 0.f : (virt ? a.s.T[w] : a.tree.rootT[idx]);
+    k.cost_new[w] = cost0 + step;
+    k.rootT_new[w] = root0;
 }
 
 // ---------------------------------------------------------------------------
@@ -552,20 +596,37 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
     const int64_t avail = pool_cap(a.tree, p) - snap;
     int64_t running = 0;
     if (tid == 0) s_last = 0;
-    for (int64_t c0 = 0; c0 < a.B; c0 += blockDim.x) {
-        const int64_t w = c0 + tid;
-        int need = 0;
-        bool virt = false;
-        if (w < a.B && k.edge_valid[w] && worker_pool(a.s.dir[w], a.s.grp[w]) == p) {
-            if (!k.edge_free[w]) {
-                k.status[w] = ST_STATUS_TRAPPED;  // the extension collides
-            } else {
-                virt = k.parent[w] < 0;
-                need = virt ? 2 : 1;
-            }
+    // R consecutive workers per thread and pass; all their loads are issued
+    // before any store
+    constexpr int R = 4;
+    for (int64_t c0 = 0; c0 < a.B; c0 += (int64_t)blockDim.x * R) {
+        int need[R];
+        int32_t par0[R];
+        uint8_t ev[R], ef[R];
+        int8_t dr[R];
+        int32_t gr[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t w = c0 + (int64_t)tid * R + r;
+            const bool in = w < a.B;
+            ev[r] = in ? k.edge_valid[w] : 0;
+            ef[r] = in ? k.edge_free[w] : 0;
+            dr[r] = in ? a.s.dir[w] : 0;
+            gr[r] = in ? a.s.grp[w] : 0;
+            par0[r] = in ? k.parent[w] : 0;
         }
-        // block-wide exclusive prefix of `need`
-        int incl = need;
+        int tot = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            need[r] = 0;
+            if (ev[r] && worker_pool(dr[r], gr[r]) == p) {
+                if (!ef[r]) k.status[c0 + (int64_t)tid * R + r] = ST_STATUS_TRAPPED;  // the extension collides
+                else need[r] = par0[r] < 0 ? 2 : 1;
+            }
+            tot += need[r];
+        }
+        // block-wide exclusive prefix of the threads' totals (worker order)
+        int incl = tot;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int v = __shfl_up(incl, o, 64);
@@ -583,18 +644,29 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
             s_total = acc;
         }
         __syncthreads();
-        const int64_t off = running + wsum[wv] + incl - need;
-        if (need > 0) {
-            if (off + need > avail) {
+        int64_t off = running + wsum[wv] + incl - tot;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (need[r] == 0) continue;
+            const int64_t w = c0 + (int64_t)tid * R + r;
+            if (off + need[r] > avail) {
                 k.status[w] = ST_STATUS_DROPPED;
                 pl->overflow = 1;
             } else {
                 int64_t idx = base + snap + off;
-                int32_t par = k.parent[w];
+                int32_t par = par0[r];
+                const bool virt = par < 0;
+                // all loads first: the tree stores may alias them for the compiler
+                float xv[kMaxDof + 1];
+#pragma unroll
+                for (int jj = 0; jj <= kMaxDof; ++jj) xv[jj] = jj <= d ? k.xnew[w * W + jj] : 0.f;
+                const float cn = k.cost_new[w], rn = k.rootT_new[w];
+                const float T = a.s.T[w];
                 if (virt) {
                     // materialise the backward tree rooted at (q_g, T)
-                    const float T = a.s.T[w];
-                    for (int j = 0; j < d; ++j) a.tree.x[(int64_t)j * a.tree.total + idx] = a.sc.q_g[j];
+#pragma unroll
+                    for (int jj = 0; jj < kMaxDof; ++jj)
+                        if (jj < d) a.tree.x[(int64_t)jj * a.tree.total + idx] = a.sc.q_g[jj];
                     a.tree.x[(int64_t)d * a.tree.total + idx] = T;
                     a.tree.parent[idx] = -1;
                     a.tree.cost[idx] = 0.f;
@@ -604,14 +676,17 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
                     k.parent[w] = par;
                     ++idx;
                 }
-                for (int j = 0; j <= d; ++j) a.tree.x[(int64_t)j * a.tree.total + idx] = k.xnew[w * W + j];
+#pragma unroll
+                for (int jj = 0; jj <= kMaxDof; ++jj)
+                    if (jj <= d) a.tree.x[(int64_t)jj * a.tree.total + idx] = xv[jj];
                 a.tree.parent[idx] = par;
-                a.tree.cost[idx] = k.cost_new[w];
-                a.tree.rootT[idx] = k.rootT_new[w];
+                a.tree.cost[idx] = cn;
+                a.tree.rootT[idx] = rn;
                 k.new_idx[w] = (int32_t)idx;
                 k.status[w] = ST_STATUS_ADVANCED;
-                atomicMax(&s_last, (int)(off + need));
+                atomicMax(&s_last, (int)(off + need[r]));
             }
+            off += need[r];
         }
         running += s_total;
         __syncthreads();
@@ -658,19 +733,30 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
     k.Up[w] = INFINITY;
     k.Cp[w] = INFINITY;
     if (!adv || bi == 0xffffffffu) return;
+    // all loads first: the stores may alias them for the compiler
+    float y[kMaxDof + 1], xn[kMaxDof + 1];
+#pragma unroll
+    for (int j = 0; j <= kMaxDof; ++j) {
+        y[j] = j <= d ? a.tree.x[(int64_t)j * a.tree.total + bi] : 0.f;
+        xn[j] = j < d ? k.xnew[w * W + j] : 0.f;
+    }
+    const float up = a.dir[w] == 0 ? a.tree.rootT[bi] : k.rootT_new[w];
+    const float cp = k.cost_new[w], cb = a.tree.cost[bi];
     float D2 = 0.f;
-    for (int j = 0; j <= d; ++j) {
-        const float v = a.tree.x[(int64_t)j * a.tree.total + bi];
-        k.xb[w * W + j] = v;
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j) {
         if (j < d) {
-            const float e = v - k.xnew[w * W + j];
+            const float e = y[j] - xn[j];
             D2 = fmaf(e, e, D2);
         }
     }
+#pragma unroll
+    for (int j = 0; j <= kMaxDof; ++j)
+        if (j <= d) k.xb[w * W + j] = y[j];
     k.bridge[w] = (int32_t)bi;
     k.br_valid[w] = 1;
-    k.Up[w] = a.dir[w] == 0 ? a.tree.rootT[bi] : k.rootT_new[w];
-    k.Cp[w] = k.cost_new[w] + sqrtf(D2) + a.tree.cost[bi];
+    k.Up[w] = up;
+    k.Cp[w] = cp + sqrtf(D2) + cb;
 }
 
 // ---------------------------------------------------------------------------
@@ -719,20 +805,25 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
     if (tid == 0) {
         PlanDev *pl = a.pl;
         const int w = sW[0];
-        if (w >= 0 && (sU[0] < pl->U || (sU[0] == pl->U && sC[0] < pl->C))) {
-            pl->improved = sU[0] < pl->U ? 2 : 1;
+        // every load before the first store
+        const float U0 = pl->U, C0 = pl->C;
+        const int32_t it = pl->iter, fi = pl->first_iter;
+        int8_t dw = 0;
+        int32_t ni = -1, bw = -1;
+        if (w >= 0) {
+            dw = a.dir[w];
+            ni = k.new_idx[w];
+            bw = k.bridge[w];
+        }
+        if (w >= 0 && (sU[0] < U0 || (sU[0] == U0 && sC[0] < C0))) {
+            pl->improved = sU[0] < U0 ? 2 : 1;
             pl->U = sU[0];
             pl->C = sC[0];
-            if (a.dir[w] == 0) {
-                pl->inc_f = k.new_idx[w];
-                pl->inc_b = k.bridge[w];
-            } else {
-                pl->inc_f = k.bridge[w];
-                pl->inc_b = k.new_idx[w];
-            }
-            if (pl->first_iter < 0) pl->first_iter = pl->iter;
+            pl->inc_f = dw == 0 ? ni : bw;
+            pl->inc_b = dw == 0 ? bw : ni;
+            if (fi < 0) pl->first_iter = it;
         }
-        pl->iter += 1;
+        pl->iter = it + 1;
     }
     // optional caller outputs
     const st_extend_out &o = a.out;
@@ -1117,7 +1208,6 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     pa.order = w.order;
     pa.tiles = (int4 *)w.tiles;
     pa.n_tiles = w.n_tiles;
-    pa.qbuf = w.xb;  // AoS queries (xb is free until the bridge stage)
     pa.keys = w.nn_key;
     pa.mode = 0;
     a.mt_nn = max_tiles(B, np);
@@ -1128,7 +1218,12 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     sa.use_snap = 1;
     sa.variant = p->prm.variant;
     sa.v = p->sc.v;
-    sa.qbuf = w.xb;
+    // the samples themselves (SoA) are the queries
+    sa.qx = in.qr;
+    sa.sq = 1;
+    sa.sj = B;
+    sa.qt = in.tr;
+    sa.st = 1;
     sa.order = w.order;
     sa.tiles = (const int4 *)w.tiles;
     sa.n_tiles = w.n_tiles;
@@ -1165,7 +1260,12 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     a.mt_br = max_tiles(B, 2);
     ScanArgs &sb = a.scan_br;
     sb = sa;
-    sb.qbuf = w.xnew;
+    // the new nodes (AoS [B][d+1]) are the queries
+    sb.qx = w.xnew;
+    sb.sq = d + 1;
+    sb.sj = 1;
+    sb.qt = w.xnew + d;
+    sb.st = d + 1;
     sb.keys = nullptr;
     sb.pkey = w.br_key;
     sb.pidx = w.br_idx;
@@ -1302,7 +1402,11 @@ int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64
     sa.use_snap = 0;
     sa.variant = p->prm.variant;
     sa.v = p->sc.v;
-    sa.qbuf = xq;
+    sa.qx = xq;
+    sa.sq = p->d + 1;
+    sa.sj = 1;
+    sa.qt = xq + p->d;
+    sa.st = p->d + 1;
     sa.order = nullptr;
     sa.tiles = (const int4 *)w.tiles;
     sa.n_tiles = w.n_tiles;

@@ -31,7 +31,6 @@ struct PrepArgs {
     int32_t *set_of, *order;
     int4 *tiles;
     int32_t *n_tiles;
-    float *qbuf;        // mode 0: AoS copy of the queries
     unsigned long long *keys;
     int32_t mode;       // 0 nearest node, 1 bridges
 };
@@ -41,7 +40,9 @@ struct ScanArgs {
     const PlanDev *pl;
     int32_t use_snap, variant;
     float v;
-    const float *qbuf;      // AoS queries [.][d+1]
+    // query q: coordinate j at qx[q sq + j sj] (j < d), time at qt[q st]
+    const float *qx, *qt;
+    int64_t sq, sj, st;
     const int32_t *order;   // query ids per tile slot (null: identity)
     const int4 *tiles;
     const int32_t *n_tiles;
