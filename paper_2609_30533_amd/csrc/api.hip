@@ -547,6 +547,16 @@ int st_set_state_split(st_problem *p, int32_t split_extension, int32_t split_bri
     return ST_OK;
 }
 
+int st_set_flat_extension(st_problem *p, int32_t edges_per_block) {
+    if (!p) return fail(ST_EINVAL, "null problem");
+    if (edges_per_block < 0 || edges_per_block > 8)
+        return fail(ST_EINVAL, "edges per block must be 0 (chunked path) to 8");
+    p->flat_ext = edges_per_block;
+    ST_HIP(hipDeviceSynchronize());
+    graphs_free(p);
+    return ST_OK;
+}
+
 int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out, void *stream) {
     if (!p || M < 0 || (M > 0 && (!x || !free_out))) return fail(ST_EINVAL, "st_check_states: bad arguments");
     ST_HIP(launch_check_states(p->sc, M, x, free_out, (hipStream_t)stream));

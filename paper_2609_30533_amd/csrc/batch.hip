@@ -155,6 +155,7 @@ static int batch_build(st_batch *b) {
         L.nb_edge = std::max(L.nb_edge, std::max(a.edge_ext.nb_edge, a.edge_br.nb_edge));
         L.nb_merge = std::max<int>(L.nb_merge, (int)((B * 64 + 255) / 256));
         L.max_pools = std::max(L.max_pools, p->tree.n_pools);
+        L.ext_flat = L.ext_flat && a.edge_ext.flat > 0;
         const std::vector<void *> sb = member_bufs(p);
         b->saved_bufs.insert(b->saved_bufs.end(), sb.begin(), sb.end());
     }
@@ -187,6 +188,7 @@ static int batch_build(st_batch *b) {
             c.nb_sample = std::max(c.nb_sample, smp[m].nb);
             c.nb_items_ext = std::max(c.nb_items_ext, edge_ext[m].nb_items);
             c.nb_items_br = std::max(c.nb_items_br, edge_br[m].nb_items);
+            if (edge_ext[m].flat > 0) c.nb_flat = std::max(c.nb_flat, flat_blocks(edge_ext[m].E, edge_ext[m].flat));
             c.lds = std::max(c.lds, scene_lds_bytes(b->mem[m]->sc));
         }
         ST_HIP(upload(b->owned, kv.second, &c.members));

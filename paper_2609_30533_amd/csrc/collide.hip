@@ -248,6 +248,137 @@ __device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
     if (bx == 0 && threadIdx.x < eb.mmax) eb.cnt[threadIdx.x * kCntStride] = 0;
 }
 
+// ---------------------------------------------------------------------------
+// Short edges, flattened: one wave per block takes kFlatEdges consecutive
+// edges, lays their states end to end (edge after edge, state order inside
+// an edge) over its 64 lanes in rounds, and decides them completely: state
+// count, checks, free / first hit and the work counters, in one kernel.  A
+// lane skips a state above a hit already found for its edge; within a round
+// the lanes of one edge form the group of the FIRST rule, so the least
+// colliding index is exact.  Meant for edges of bounded length (extensions):
+// a long edge would serialise its rounds in one wave.
+// ---------------------------------------------------------------------------
+
+constexpr int kFlatEdges = 8;  // edges per block at most (a.flat of them)
+
+template <int KIND, int OT, int OBS>
+__device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, int bx) {
+    __shared__ float s_A[kFlatEdges][kMaxDof + 1], s_B[kFlatEdges][kMaxDof + 1];
+    __shared__ int32_t s_off[kFlatEdges + 1], s_n[kFlatEdges], s_hit[kFlatEdges];
+    const SceneDev &sc = a.sc;
+    const int d = sc.d, W = d + 1;
+    const int lane = threadIdx.x;  // one wave per block
+    const int EB = a.flat;
+    const int64_t e0 = (int64_t)bx * EB;
+    stage_obstacles(sc, lds);
+    if (lane < kFlatEdges) {
+        const int64_t e = e0 + lane;
+        int32_t n = -1;
+        if (lane < EB && e < a.E && !(a.valid && !a.valid[e])) {
+            const float *A = a.xa + e * W, *B = a.xb + e * W;
+            if (A[d] > B[d]) { const float *tmp = A; A = B; B = tmp; }
+            double D2 = 0.0;
+            for (int j = 0; j < d; ++j) {
+                const double dq = (double)B[j] - (double)A[j];
+                D2 += dq * dq;
+            }
+            const double span = fmax(sqrt(D2), sc.v_d * ((double)B[d] - (double)A[d]));
+            int64_t nn = (int64_t)ceil(span / sc.h_d);
+            if (nn < 1) nn = 1;
+            if (nn > (1ll << 30)) nn = 1ll << 30;
+            n = (int32_t)nn;
+            for (int j = 0; j <= kMaxDof; ++j) {
+                s_A[lane][j] = j <= d ? A[j] : 0.f;
+                s_B[lane][j] = j <= d ? B[j] : 0.f;
+            }
+        }
+        s_n[lane] = n;
+        s_hit[lane] = kNoHit;
+    }
+    __syncthreads();
+    if (lane == 0) {
+        int acc = 0;
+        for (int i = 0; i < kFlatEdges; ++i) {
+            s_off[i] = acc;
+            acc += s_n[i] >= 0 ? s_n[i] + 1 : 0;
+        }
+        s_off[kFlatEdges] = acc;
+    }
+    __syncthreads();
+    const int total = s_off[kFlatEdges];
+    for (int base = 0; base < total; base += 64) {
+        const int g = base + lane;
+        int i = 0;
+#pragma unroll
+        for (int k = 1; k < kFlatEdges; ++k) i += g >= s_off[k] ? 1 : 0;
+        const int j = g - s_off[i];
+        const int32_t n = s_n[i];
+        // a state above a known hit of its edge is not needed
+        const bool act = g < total && j <= s_hit[i];
+        // lanes of this edge in this round: its group for the FIRST rule
+        const int lo = max(s_off[i] - base, 0), hi = min(s_off[i + 1] - base, 64);
+        const uint64_t seg = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
+        const uint64_t lower = seg & ((1ull << lane) - 1ull);
+        float q[kMaxDof];
+        float t = 0.f;
+        if (act && j == n) {
+            // the last state is the endpoint itself
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) q[k] = k < d ? s_B[i][k] : 0.f;
+            t = s_B[i][d];
+        } else if (act) {
+            const float sj = (float)j * (1.0f / (float)n);
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) q[k] = k < d ? fmaf(sj, s_B[i][k] - s_A[i][k], s_A[i][k]) : 0.f;
+            t = fmaf(sj, s_B[i][d] - s_A[i][d], s_A[i][d]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < kMaxDof; ++k) q[k] = 0.f;
+        }
+        const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, q, t, act, seg, lower);
+        if (hit && act) atomicMin(&s_hit[i], j);
+        __syncthreads();
+    }
+    // results and work counters
+    unsigned long long states = 0, edges = 0;
+    if (lane < EB) {
+        const int64_t e = e0 + lane;
+        const int32_t n = s_n[lane];
+        if (e < a.E && n >= 0) {
+            const int32_t h = s_hit[lane];
+            const bool fr = h == kNoHit;
+            a.free_out[e] = fr ? 1 : 0;
+            if (a.first_hit) a.first_hit[e] = fr ? -1 : h;
+            states = fr ? (unsigned long long)n + 1ull : (unsigned long long)h + 1ull;
+            edges = 1;
+        }
+    }
+    if (a.work) {
+        for (int o = 32; o > 0; o >>= 1) {
+            states += __shfl_down(states, o, 64);
+            edges += __shfl_down(edges, o, 64);
+        }
+        if (lane == 0 && edges) {
+            atomicAdd(&a.work[0], edges);
+            atomicAdd(&a.work[1], states);
+        }
+    }
+}
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(64) void k_edge_flat(EdgeArgs a) {
+    extern __shared__ float4 lds[];
+    edge_flat_body<KIND, OT, OBS>(a, lds, blockIdx.x);
+}
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(64) void k_edge_flat_multi(const EdgeArgs *av, const int32_t *members) {
+    extern __shared__ float4 lds[];
+    const EdgeArgs &a = av[members[blockIdx.y]];
+    if ((int64_t)blockIdx.x * a.flat >= a.E) return;
+    edge_flat_body<KIND, OT, OBS>(a, lds, blockIdx.x);
+}
+
 __global__ __launch_bounds__(256) void k_edge_plan(EdgeArgs a) { edge_plan_body(a, blockIdx.x); }
 
 template <int KIND, int OT, int OBS, int SPLIT>
@@ -391,7 +522,12 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
     const int64_t per_block = 4 * (int64_t)(64 >> lpe_shift);
     const int64_t want = (E + per_block - 1) / per_block;
     a.nb_items = (int)std::min<int64_t>(std::max<int64_t>(want, min_item_blocks), 8192);
+    a.flat = 0;
     return a;
+}
+
+int flat_blocks(int64_t E, int edges_per_block) {
+    return (int)((E + edges_per_block - 1) / edges_per_block);
 }
 
 hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
@@ -405,6 +541,13 @@ hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E,
 
 hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
     if (a.E <= 0) return hipSuccess;
+    if (a.flat) {
+        dispatch_scene(a.sc, [&](auto kind, auto ot, auto obs) {
+            k_edge_flat<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+                <<<dim3(flat_blocks(a.E, a.flat)), dim3(64), scene_lds_bytes(a.sc), s>>>(a);
+        });
+        return hipGetLastError();
+    }
     if (a.E > a.eb.cap) return hipErrorInvalidValue;
     k_edge_plan<<<a.nb_edge, 256, 0, s>>>(a);
     const size_t lds = scene_lds_bytes(a.sc);
@@ -413,6 +556,15 @@ hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
             <<<dim3(a.nb_items), dim3(256), lds, s>>>(a);
     });
     k_edge_finish<<<a.nb_edge, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_flat_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
+                                  int n_members, int max_blocks, size_t lds, hipStream_t s) {
+    dispatch_scene(cls, [&](auto kind, auto ot, auto obs) {
+        k_edge_flat_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+            <<<dim3(max_blocks, n_members), dim3(64), lds, s>>>(d_args, d_members);
+    });
     return hipGetLastError();
 }
 

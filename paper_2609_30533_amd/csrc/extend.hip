@@ -1243,6 +1243,9 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     a.edge_ext = edge_args(p->sc, p->ebufs, B, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit,
                            edge_shift(p, false), p->d_plan->work, min_item_blocks,
                            split_for(p->split_ext, launch_edges));
+    // extension edges are short (rho <= eta: at most ceil(sqrt(2) eta / h) + 1
+    // states): the flattened path, unless eta / h is unusually large
+    a.edge_ext.flat = std::sqrt(2.0) * p->prm.eta / p->prm.h <= 4096.0 ? p->flat_ext : 0;
     // insertion (a5)
     InsertArgs &ia = a.insert;
     ia.sc = p->sc;
@@ -1366,10 +1369,15 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
             <<<dim3(L.mt_nn, L.nch, L.n_rr), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.rr_members);
     k_steer<true><<<dim3(L.nb_worker, L.P), 256, 0, s>>>(SteerArgs{}, L.steer);
     ST_HIP(hipGetLastError());
-    ST_HIP(launch_edge_plan_multi(L.edge_ext, L.P, L.nb_edge, s));
-    for (const BatchClass &c : L.classes)
-        ST_HIP(launch_edge_items_multi(c.key, c.split_ext, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));
-    ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
+    if (L.ext_flat) {
+        for (const BatchClass &c : L.classes)
+            ST_HIP(launch_edge_flat_multi(c.key, L.edge_ext, c.members, c.n, c.nb_flat, c.lds, s));
+    } else {
+        ST_HIP(launch_edge_plan_multi(L.edge_ext, L.P, L.nb_edge, s));
+        for (const BatchClass &c : L.classes)
+            ST_HIP(launch_edge_items_multi(c.key, c.split_ext, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));
+        ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
+    }
     k_insert<true><<<dim3(L.max_pools, L.P), 1024, 0, s>>>(InsertArgs{}, L.insert);
     k_prep<true><<<dim3(1, L.P), 1024, 0, s>>>(PrepArgs{}, L.prep_br);
     k_scan<kScanBridge, true><<<dim3(L.mt_br, L.nch, L.P), kTileQ, 0, s>>>(ScanArgs{}, L.scan_br, L.all_members);

@@ -113,6 +113,7 @@ struct EdgeArgs {
     int32_t split_shift;        // lanes per state = 1 << split_shift
     int32_t nb_edge;            // blocks of the per-edge kernels
     int32_t nb_items;           // blocks of the item kernel
+    int32_t flat;               // > 0: short edges, flattened one-kernel path, this many per block
 };
 
 // Per-batch work buffers (capacity Bcap workers).
@@ -179,6 +180,8 @@ struct st_problem {
     int tune_ext = 5, tune_br = 6, tune_api = 5;
     // lanes per state (log2) for the same three launches; -1 chooses by size
     int split_ext = -1, split_br = -1, split_api = -1;
+    // extension edges per block of the flattened path (0: chunked item path)
+    int flat_ext = 4;
     hipGraphExec_t graph[2] = {nullptr, nullptr};
     int64_t graph_B = 0;
     hipStream_t cap_stream = nullptr;
@@ -213,6 +216,10 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
                    const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
                    unsigned long long *work, int min_item_blocks, int split_shift);
 hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s);
+// The flattened path: blocks for E edges, and its many-problem launch.
+int flat_blocks(int64_t E, int edges_per_block);
+hipError_t launch_edge_flat_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
+                                  int n_members, int max_blocks, size_t lds, hipStream_t s);
 // The same pipeline for P problems at once (records in device memory); the
 // item kernel runs once per scene class over its member records.
 hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);

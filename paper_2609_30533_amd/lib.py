@@ -85,7 +85,7 @@ EXPORTS = [
     "st_problem_create", "st_problem_destroy", "st_problem_reset", "st_check_states", "st_check_edges",
     "st_nearest", "st_sample_batch", "st_extend_batch", "st_iterate", "st_plan", "st_path_free", "st_get_info",
     "st_tree_export", "st_tree_import", "st_slots_export", "st_goal_grid_export", "st_partition_export",
-    "st_set_tuning", "st_set_state_split", "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
+    "st_set_tuning", "st_set_state_split", "st_set_flat_extension", "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
     "st_mlp_create", "st_mlp_destroy", "st_mlp_param_count", "st_mlp_params", "st_mlp_grads", "st_mlp_forward",
     "st_mlp_loss", "st_mlp_backward", "st_mlp_adam", "st_proposal_set",
     "st_path_get", "st_batch_create", "st_batch_destroy", "st_batch_iterate", "st_batch_plan",
@@ -130,6 +130,7 @@ def load():
     L.st_partition_export.argtypes = [vp, vp, vp, vp, i32]
     L.st_set_tuning.argtypes = [vp, i32, i32, i32, i32]
     L.st_set_state_split.argtypes = [vp, i32, i32, i32]
+    L.st_set_flat_extension.argtypes = [vp, i32]
     L.st_profile_enable.argtypes = [vp, i32]
     L.st_profile_read.argtypes = [vp, vp, vp]
     L.st_work_counters.argtypes = [vp, vp]
@@ -368,6 +369,10 @@ class Problem:
     def set_state_split(self, extension=0, bridge=0, check=0):
         """Lanes per state (1, 2, 4; -1 by launch size; 0 keeps)."""
         _check(self.L.st_set_state_split(self.h, extension, bridge, check), "st_set_state_split")
+
+    def set_flat_extension(self, edges_per_block):
+        """Extension edges per block of the flattened path (0: chunked path)."""
+        _check(self.L.st_set_flat_extension(self.h, int(edges_per_block)), "st_set_flat_extension")
 
     def set_proposal(self, z=None, mix=0.5, stream=None):
         """Install the network output z (device tensor [168]) for this problem."""

@@ -242,3 +242,33 @@ def test_invalid_arguments_are_errors():
     with pytest.raises(lib.StError):
         lib.Problem(prob)
     torch_cuda()
+
+
+@pytest.mark.parametrize("make", [lambda: _small(scenes.arm6(2), 1024, groups=8),
+                                  lambda: _small(scenes.disc2d(0), 512)], ids=["arm6", "disc2d"])
+def test_extension_paths_agree(make):
+    """The flattened and the chunked extension-edge paths decide identically,
+    so the planner's trees after some iterations are equal bit for bit."""
+    from paper_2609_30533_amd.lib import Problem
+    torch = torch_cuda()
+    prob = make()
+    banner("extension paths %s" % prob.name)
+    states = []
+    for epb in (0, 1, 2, 8):
+        gp = Problem(prob)
+        gp.set_flat_extension(epb)
+        gp.iterate(12)
+        torch.cuda.synchronize()
+        st = gp.export()
+        c = st["counts"]
+        p = prob.params
+        rows = np.concatenate([np.arange(0 if k == 0 else p.cap_fwd + (k - 1) * p.cap_bwd,
+                                         (0 if k == 0 else p.cap_fwd + (k - 1) * p.cap_bwd) + int(n))
+                               for k, n in enumerate(c)])
+        states.append((c, st["x"][rows], st["parent"][rows], gp.work_counters()))
+        gp.close()
+    for c, x, par, w in states[1:]:
+        assert np.array_equal(c, states[0][0])
+        assert np.array_equal(x, states[0][1])
+        assert np.array_equal(par, states[0][2])
+        assert w["edges"] == states[0][3]["edges"] and w["edge_states"] == states[0][3]["edge_states"]
