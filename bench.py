@@ -147,6 +147,26 @@ def ttfs_section(lib, args):
     tp, Up = single["plain"]
     common = [s for s in solvable if s in tp and math.isfinite(fl[s])]
 
+    # the same comparison as a workload: the first Q evaluation problems
+    # submitted together; plain answers them one after another (each with its
+    # budget), the learned batch answers them all at once.  A problem's time
+    # is from the submission of the workload to its first solution.
+    Q = args.queue_problems
+    queue = {}
+    if Q > 0:
+        t0 = time.perf_counter()
+        for s in range(Q):
+            p = eval_problem(s, B=4096, cap_fwd=1 << 18, cap_bwd=1 << 16)
+            g = lib.Problem(p)
+            ts = (time.perf_counter() - t0) * 1e3
+            r = g.plan(max_ms=args.queue_ms, stop_at_first=True, iters_per_sync=1)
+            if r["first_iter"] >= 0:
+                queue[s] = ts + r["first_ms"]
+            g.close()
+        plain_queue_wall = (time.perf_counter() - t0) * 1e3
+        lq = batched_run(lib, [eval_problem(s) for s in range(Q)], args.queue_ms, proposal=prop)
+        qcommon = [s for s in queue if math.isfinite(lq["first_ms"][s])]
+
     def med(v):
         return float(np.median(v)) if len(v) else None
 
@@ -169,6 +189,14 @@ def ttfs_section(lib, args):
         "solved_learned_batched": int(learned_b["n_solved"]),
         "batched_wall_ms": float(learned_b["total_ms"]),
         "plain_sequential_wall_ms_solvable": float(sum(tp.values()) + args.ttfs_single_ms * (len(solvable) - len(tp))),
+        "queue_workload": "the first %d evaluation problems submitted at once; %.0f ms budget per problem (plain, "
+                          "one after another) or for the whole batch (learned+batched); time from submission to "
+                          "each problem's first solution, median over problems both solve" % (Q, args.queue_ms),
+        "queue_ms_median_plain": med([queue[s] for s in qcommon]) if Q > 0 else None,
+        "queue_ms_median_learned_batched": med([float(lq["first_ms"][s]) for s in qcommon]) if Q > 0 else None,
+        "queue_common": len(qcommon) if Q > 0 else 0,
+        "queue_wall_ms_plain": plain_queue_wall if Q > 0 else None,
+        "queue_wall_ms_learned_batched": float(lq["total_ms"]) if Q > 0 else None,
     }
 
 
@@ -240,6 +268,8 @@ def main():
     ap.add_argument("--ttfs-batch", type=int, default=512, help="evaluation problems (0: skip the comparison)")
     ap.add_argument("--ttfs-ms", type=float, default=2000.0, help="budget of each batched evaluation run")
     ap.add_argument("--ttfs-single-ms", type=float, default=1000.0, help="budget of each single-problem run")
+    ap.add_argument("--queue-problems", type=int, default=128, help="problems of the workload comparison (0: skip)")
+    ap.add_argument("--queue-ms", type=float, default=100.0)
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
