@@ -259,6 +259,36 @@ def edge_sweep(lib, scenes, n_edges, reps=5):
     return out
 
 
+def ablation(lib, scenes, args):
+    """Allocation ablation (Sec. VI): root recycling against fixed roots
+    (deactivation only) as the arrival range widens, 16 roots and 512
+    samples per iteration, on disc problems whose obstacles move during the
+    first 10 s (the 7-DOF stand-ins are rarely solvable); each condition is
+    one batch of the same problems with the same budget; mean final arrival
+    over the problems both solve."""
+    out = []
+    for H in (10.0, 25.0, 50.0, 100.0):
+        res = {}
+        for nr in (0, 1):
+            probs = []
+            for s in range(args.ablation):
+                p = scenes.disc2d(s, horizon=10.0, t_min=0.0,
+                                  params=scenes.Params(variant=scenes.VARIANT_RR, n_groups=16, batch=512, eta=0.1,
+                                                       h=0.01, cap_fwd=1 << 16, cap_bwd=1 << 12, seed=1,
+                                                       no_recycling=nr))
+                p.t_max = scenes.f32(H)
+                probs.append(p)
+            res[nr] = batched_run(lib, probs, args.ablation_ms)
+        both = np.isfinite(res[0]["U"]) & np.isfinite(res[1]["U"])
+        out.append({"workload": "disc2d, 8 moving discs, range [0, %g] s" % H, "roots": 16, "samples": 512,
+                    "budget_ms": args.ablation_ms, "problems": args.ablation,
+                    "solved_recycling": int(res[0]["n_solved"]), "solved_no_recycling": int(res[1]["n_solved"]),
+                    "common": int(both.sum()),
+                    "mean_arrival_recycling": float(np.mean(res[0]["U"][both])) if both.any() else None,
+                    "mean_arrival_no_recycling": float(np.mean(res[1]["U"][both])) if both.any() else None})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -273,6 +303,9 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--ablation", type=int, default=0,
+                    help="only run the recycling ablation on this many problems per condition and print JSON")
+    ap.add_argument("--ablation-ms", type=float, default=1000.0)
     ap.add_argument("--edge-sweep", type=int, default=0,
                     help="only time st_check_edges on this many synthetic edges per launch shape and print JSON")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -286,6 +319,11 @@ def main():
     from paper_2609_30533_amd import lib, scenes
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.init()
+
+    if args.ablation > 0:
+        for r in ablation(lib, scenes, args):
+            print(json.dumps(r), flush=True)
+        return
 
     if args.edge_sweep > 0:
         for r in edge_sweep(lib, scenes, args.edge_sweep):

@@ -89,6 +89,8 @@ typedef struct st_params {
     int32_t cap_bwd;     /* capacity of each backward pool (one per group / slot) */
     uint32_t seed;       /* Philox4x32-10 key word 0 */
     uint32_t problem_id; /* Philox4x32-10 key word 1 */
+    int32_t no_recycling;/* recycling variant: 1 keeps the initial roots, deactivation
+                            only (the allocation ablation of Sec. VI); 0 recycles (Alg. 3) */
 } st_params;
 
 /* Problem description (Sec. III): robot, configuration box C, start q_s,

@@ -49,7 +49,7 @@ class Scene(C.Structure):
         ("eta", C.c_double), ("h", C.c_double), ("dt", C.c_double),
         ("p_new", C.c_double), ("p_guided", C.c_double),
         ("cap_fwd", C.c_int32), ("cap_bwd", C.c_int32),
-        ("seed", C.c_uint32), ("problem_id", C.c_uint32),
+        ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("no_recycling", C.c_int32),
     ]
 
 
@@ -164,6 +164,7 @@ def make_scene(prob, problem_id: int = 0) -> Scene:
     s.eta, s.h, s.dt, s.p_new, s.p_guided = p.eta, p.h, p.dt, p.p_new, p.p_guided
     s.cap_fwd, s.cap_bwd = p.cap_fwd, p.cap_bwd
     s.seed, s.problem_id = p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF
+    s.no_recycling = 1 if getattr(p, "no_recycling", 0) else 0
     return s
 
 

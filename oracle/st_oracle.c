@@ -599,7 +599,8 @@ static void rr_init_roots(orc_planner *p) {
  * strata; walking the strata that hold no retained active root in time order,
  * each gives its first free grid time to the next donor (slot order).  A
  * donor that receives a root discards its tree (generation + 1) and gets the
- * empty root; a donor without one stays inactive. */
+ * empty root; a donor without one stays inactive.  The no-recycling ablation
+ * of the evaluation (Sec. VI) keeps the initial roots: deactivation only. */
 static void rr_update(orc_planner *p) {
     int N = p->sc.n_groups;
     double U = p->U;
@@ -611,6 +612,7 @@ static void rr_update(orc_planner *p) {
     int64_t k_end = p->k_lo;
     while (k_end <= p->k_hi && grid_time(p, k_end) < U) ++k_end;
     int64_t K = k_end - p->k_lo;
+    if (p->sc.no_recycling) K = 0;
     int di = 0;
     double xg[ORC_MAX_DOF + 1];
     for (int j = 0; j < p->sc.d; ++j) xg[j] = p->sc.q_g[j];

@@ -58,6 +58,7 @@ typedef struct orc_scene {
     double eta, h, dt, p_new, p_guided;
     int32_t cap_fwd, cap_bwd;
     uint32_t seed, problem_id;
+    int32_t no_recycling;               /* recycling variant: 1 = roots fixed, deactivation only (ablation) */
 } orc_scene;
 
 typedef struct orc_planner orc_planner;

@@ -101,6 +101,7 @@ static int validate(const st_problem_desc *D) {
     }
     const st_params &P = D->params;
     if (P.variant != ST_INTERVAL_ROOT && P.variant != ST_ROOT_RECYCLING) return fail(ST_EINVAL, "variant %d", P.variant);
+    if (P.no_recycling != 0 && P.no_recycling != 1) return fail(ST_EINVAL, "no_recycling %d", P.no_recycling);
     if (P.n_groups < 1 || P.n_groups > ST_MAX_GROUPS) return fail(ST_EINVAL, "n_groups %d", P.n_groups);
     if (P.batch < 1) return fail(ST_EINVAL, "batch %d", P.batch);
     if (!(P.eta > 0) || !(P.h > 0) || !(P.dt > 0) || !finite(P.eta) || !finite(P.h) || !finite(P.dt))

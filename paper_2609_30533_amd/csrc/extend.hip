@@ -903,7 +903,8 @@ __global__ __launch_bounds__(256) void k_roots(RootsArgs a0, const RootsArgs *av
         s_kend = k;
     }
     __syncthreads();
-    const int64_t K = s_kend - w.k_lo;
+    // the no-recycling ablation keeps the initial roots: deactivation only
+    const int64_t K = a.no_recycling ? 0 : s_kend - w.k_lo;
     if (tid < N && K > 0) {
         const int64_t a0 = w.k_lo + (K * tid) / N, b0 = w.k_lo + (K * (tid + 1)) / N;
         bool occupied = false;
@@ -1298,6 +1299,7 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ra.pl = p->d_plan;
     ra.variant = p->prm.variant;
     ra.N = p->prm.n_groups;
+    ra.no_recycling = p->prm.no_recycling;
 }
 
 int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s) {

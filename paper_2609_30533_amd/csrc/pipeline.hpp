@@ -96,6 +96,7 @@ struct RootsArgs {
     WindowsDev win;
     PlanDev *pl;
     int32_t variant, N;
+    int32_t no_recycling;  // keep the initial roots (deactivation only)
 };
 
 // Every record of one iteration of one problem.

@@ -33,7 +33,7 @@ class Params(C.Structure):
                 ("eta", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("p_new", C.c_double), ("p_guided", C.c_double),
                 ("cap_fwd", C.c_int32), ("cap_bwd", C.c_int32),
-                ("seed", C.c_uint32), ("problem_id", C.c_uint32)]
+                ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("no_recycling", C.c_int32)]
 
 
 class Desc(C.Structure):
@@ -215,7 +215,8 @@ class Problem:
         D.obstacle_radius = arr(prob.obs_r, np.float64)
         p = prob.params
         D.params = Params(p.variant, p.n_groups, p.batch, p.eta, p.h, p.dt, p.p_new, p.p_guided, p.cap_fwd,
-                          p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF)
+                          p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF,
+                          1 if getattr(p, "no_recycling", 0) else 0)
         h = C.c_void_p()
         _check(self.L.st_problem_create(C.byref(D), C.byref(h)), "st_problem_create")
         self.h = h

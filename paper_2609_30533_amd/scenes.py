@@ -64,6 +64,7 @@ class Params:
     cap_fwd: int = 1 << 16     # forward-tree capacity (nodes)
     cap_bwd: int = 1 << 14     # capacity of each backward pool (group or slot)
     seed: int = 1
+    no_recycling: int = 0      # recycling variant: keep the initial roots (the paper's ablation)
 
 
 @dataclass

@@ -29,6 +29,11 @@ def _small(prob, batch, cap_f=1 << 14, cap_b=1 << 11, groups=None):
     return prob
 
 
+def _no_recycling(prob):
+    prob.params.no_recycling = 1
+    return prob
+
+
 def _to_np(s):
     return {k: v.cpu().numpy() for k, v in s.items()}
 
@@ -49,6 +54,7 @@ PROBS = [
     ("arm6-ir", lambda: _small(scenes.arm6(2), 1024, groups=8)),
     ("disc2d-rr", lambda: _small(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 512)),
     ("arm7-rr", lambda: _small(scenes.arm7rr(2, n_obs=16), 1024, groups=16)),
+    ("arm7-norecycle", lambda: _no_recycling(_small(scenes.arm7rr(2, n_obs=16), 1024, groups=16))),
     # the start configuration is grazed by an obstacle at t ~ 0.43 s: most
     # forward edges pass within 1e-4 m of contact (exempt decisions)
     ("arm6-ir-grazing", lambda: _small(scenes.arm6(1), 1024, groups=8)),

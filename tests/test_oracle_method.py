@@ -325,6 +325,44 @@ def test_root_recycling_invariants(oracle_lib):
         del out
 
 
+def test_no_recycling_keeps_the_initial_roots(oracle_lib):
+    """The allocation ablation of the evaluation: the same initial roots as
+    recycling, deactivation at a drop of U, never a replacement; until the
+    first drop of U both runs are identical."""
+    prob = scenes.arm7rr(1, n_obs=8)
+    prob.params.batch = 512
+    prob.params.cap_bwd = 1 << 12
+    rec = oracle_lib.Planner(prob)
+    prob2 = scenes.arm7rr(1, n_obs=8)
+    prob2.params.batch = 512
+    prob2.params.cap_bwd = 1 << 12
+    prob2.params.no_recycling = 1
+    fix = oracle_lib.Planner(prob2)
+    T0, act0, gen0, k0 = fix.slots()
+    Tr, actr, genr, kr = rec.slots()
+    assert np.array_equal(T0, Tr) and np.array_equal(act0, actr) and np.array_equal(k0, kr)
+    prevU, drops, same = math.inf, 0, True
+    for it in range(40):
+        s1, s2 = rec.sample(it), fix.sample(it)
+        if same:
+            assert np.array_equal(s1["qr"], s2["qr"]) and np.array_equal(s1["grp"], s2["grp"])
+        rec.extend(s1)
+        fix.extend(s2)
+        T, act, gen, kk = fix.slots()
+        assert np.array_equal(gen, gen0) and np.array_equal(kk, k0)
+        assert np.array_equal(T[act == 1], T0[act == 1])
+        assert np.all(act <= act0)
+        U = fix.info()["U"]
+        if U < prevU:
+            drops += 1
+            assert np.all(T[act == 1] < U)
+            assert np.all(act[(T0 >= U) & (act0 == 1)] == 0)
+        if drops > 0:
+            same = False  # the allocations differ from the first drop of U on
+        prevU = U
+    assert drops >= 1
+
+
 # --------------------------------------------------------------------------
 # Planner invariants and closed-form arrival cases
 # --------------------------------------------------------------------------
