@@ -205,6 +205,18 @@ int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out,
 int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
                    int32_t *first_hit, void *stream);
 
+/* Exact continuous check of edges for a translating robot (ST_ROBOT_TRANSLATE):
+ * the edge's time span is cut where an obstacle changes trajectory segment;
+ * on each piece robot and obstacle move linearly and every sphere pair's
+ * closest approach is taken in closed form, so no discretisation step is
+ * involved (an alternative to the h-discretised check of Sec. IV-B for
+ * disc-type scenes).  Free iff both endpoints lie in the box and the horizon
+ * and every pair keeps distance >= r_s + r_o (touching is free).  xa, xb:
+ * device [E][d+1]; free_out: device [E]; dmin_out: device [E] least pair
+ * clearance (may be NULL).  EINVAL for arm robots.  Async on stream. */
+int st_check_edges_continuous(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
+                              float *dmin_out, void *stream);
+
 /* ---- nearest node (Alg. 1, Eq. 7) -------------------------------------- */
 
 /* For each of M queries xq (device [M][d+1]) find the node of `set` that

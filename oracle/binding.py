@@ -99,6 +99,8 @@ def _declare(L):
     L.orc_check_states.argtypes = [S, C.c_int64, f64, u8, _opt(f64)]
     L.orc_edge_continuous.argtypes = [S, f64, f64, C.POINTER(C.c_double)]
     L.orc_edge_continuous.restype = C.c_int
+    L.orc_edge_continuous_pw.argtypes = [S, f64, f64, C.POINTER(C.c_double)]
+    L.orc_edge_continuous_pw.restype = C.c_int
     L.orc_rho.argtypes = [C.c_int, C.c_double, C.c_int, f64, f64]
     L.orc_rho.restype = C.c_double
     L.orc_nearest.argtypes = [S, C.c_int64, f64, _opt(u8), C.c_int, C.c_int, f64, C.POINTER(C.c_double),
@@ -226,6 +228,13 @@ class Oracle:
         return bool(ok), dm.value
 
     # metric ----------------------------------------------------------------
+
+    def edge_continuous_pw(self, xa, xb):
+        """Exact continuous check, obstacle trajectories cut at their waypoints."""
+        m = C.c_double()
+        ok = self.lib.orc_edge_continuous_pw(C.byref(self.scene), np.ascontiguousarray(xa, dtype=np.float64),
+                                             np.ascontiguousarray(xb, dtype=np.float64), C.byref(m))
+        return bool(ok), m.value
     def rho(self, sigma, x, xr):
         return self.lib.orc_rho(self.d, float(self.prob.v_max), int(sigma),
                                 np.ascontiguousarray(x, dtype=np.float64), np.ascontiguousarray(xr, dtype=np.float64))

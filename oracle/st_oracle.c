@@ -311,6 +311,72 @@ int orc_edge_continuous(const orc_scene *sc, const double *xa_in, const double *
     return best >= 0.0;
 }
 
+/* Exact continuous check of an edge for a translating robot against
+ * obstacles on piecewise-linear trajectories: the edge's time span is cut at
+ * every waypoint time of the obstacle strictly inside it; on each piece both
+ * the robot (linear along the edge) and the obstacle (one constant-velocity
+ * segment, or held) move linearly, so each sphere pair's relative position is
+ * affine in time and its closest approach has the closed form
+ * u* = clamp(-p0.(p1-p0) / |p1-p0|^2, 0, 1) between the piece's end values.
+ * The box and horizon hold along the edge iff they hold at both endpoints
+ * (convex sets).  Free iff they hold and every pair keeps distance >= R
+ * (touching is free); dmin receives the least pair clearance. */
+int orc_edge_continuous_pw(const orc_scene *sc, const double *xa_in, const double *xb_in, double *dmin) {
+    const int d = sc->d;
+    const double *xa = xa_in, *xb = xb_in;
+    if (xa[d] > xb[d]) { const double *tmp = xa; xa = xb; xb = tmp; }
+    int ok = 1;
+    for (int e = 0; e < 2; ++e) {
+        const double *x = e ? xb : xa;
+        if (!(x[d] >= 0.0) || !(x[d] <= sc->t_max)) ok = 0;
+        for (int j = 0; j < d; ++j)
+            if (!(x[j] >= sc->q_lo[j]) || !(x[j] <= sc->q_hi[j])) ok = 0;
+    }
+    const double ta = xa[d], tb = xb[d], T = tb - ta;
+    double best = INF;
+    for (int o = 0; o < sc->n_obs; ++o) {
+        /* piece boundaries: ta, the waypoint times strictly inside, tb */
+        double cut[ORC_MAX_WP + 2];
+        int nc = 0;
+        cut[nc++] = ta;
+        for (int k = 0; k < sc->n_wp[o]; ++k)
+            if (sc->wp[o][k][0] > ta && sc->wp[o][k][0] < tb) cut[nc++] = sc->wp[o][k][0];
+        cut[nc++] = tb;
+        for (int pc = 0; pc + 1 < nc; ++pc) {
+            const double t0 = cut[pc], t1 = cut[pc + 1];
+            double c0[3], c1[3], q0[3] = {0, 0, 0}, q1[3] = {0, 0, 0};
+            orc_obstacle_pos(sc, o, t0, c0);
+            orc_obstacle_pos(sc, o, t1, c1);
+            const double f0 = T > 0.0 ? (t0 - ta) / T : 0.0, f1 = T > 0.0 ? (t1 - ta) / T : 0.0;
+            for (int j = 0; j < d && j < 3; ++j) {
+                q0[j] = xa[j] + f0 * (xb[j] - xa[j]);
+                q1[j] = xa[j] + f1 * (xb[j] - xa[j]);
+            }
+            for (int s = 0; s < sc->n_sph; ++s) {
+                double p0[3], dp[3], pp = 0.0, pd = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    p0[c] = q0[c] + sc->sph[s][c] - c0[c];
+                    dp[c] = (q1[c] + sc->sph[s][c] - c1[c]) - p0[c];
+                    pp += dp[c] * dp[c];
+                    pd += p0[c] * dp[c];
+                }
+                double u = 0.0;
+                if (pp > 0.0) {
+                    u = -pd / pp;
+                    if (u < 0.0) u = 0.0;
+                    if (u > 1.0) u = 1.0;
+                }
+                double dist = 0.0;
+                for (int c = 0; c < 3; ++c) dist += (p0[c] + u * dp[c]) * (p0[c] + u * dp[c]);
+                dist = sqrt(dist) - (sc->sph[s][3] + sc->obs_r[o]);
+                if (dist < best) best = dist;
+            }
+        }
+    }
+    if (dmin) *dmin = best;
+    return ok && best >= 0.0;
+}
+
 /* ========================================================================= */
 /* Directed space-time distance (Eq. 7) and nearest-node search (Alg. 1).   */
 /* ========================================================================= */

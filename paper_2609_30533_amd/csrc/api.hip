@@ -245,6 +245,13 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.R2 = p->d_R2;
     sc.seg = p->d_seg;
     sc.seg_t = p->d_segt;
+    // obstacle radii for the continuous check
+    {
+        std::vector<float> radii((size_t)std::max(O, 1), 0.f);
+        for (int o = 0; o < O; ++o) radii[o] = (float)D->obstacle_radius[o];
+        if ((rc = dev_upload(&p->d_obs_r, radii.data(), radii.size())) != ST_OK) return rc;
+        sc.obs_r = p->d_obs_r;
+    }
     // sphere centres at q_g for the goal-state tests
     ST_HIP(hipMalloc((void **)&p->d_goal, std::max(S, 1) * sizeof(float4)));
     sc.goal = nullptr;
@@ -425,7 +432,7 @@ static void destroy(st_problem *p) {
     edge_bufs_free(p->ebufs);
     edge_bufs_free(p->ebufs_api);
     for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
+    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
                     p->tree.x, p->tree.parent, p->tree.cost, p->tree.rootT, p->d_plan};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -573,6 +580,16 @@ int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, u
     if (rc != ST_OK) return rc;
     ST_HIP(launch_check_edges(p->sc, p->ebufs_api, E, xa, xb, nullptr, free_out, first_hit, p->tune_api,
                               (hipStream_t)stream, nullptr, split_for(p->split_api, E)));
+    return ST_OK;
+}
+
+int st_check_edges_continuous(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
+                              float *dmin_out, void *stream) {
+    if (!p || E < 0 || (E > 0 && (!xa || !xb || !free_out)))
+        return fail(ST_EINVAL, "st_check_edges_continuous: bad arguments");
+    if (p->kind != ST_ROBOT_TRANSLATE)
+        return fail(ST_EINVAL, "st_check_edges_continuous: translating robots only");
+    ST_HIP(launch_check_edges_continuous(p->sc, E, xa, xb, free_out, dmin_out, (hipStream_t)stream));
     return ST_OK;
 }
 

@@ -32,6 +32,89 @@ __global__ __launch_bounds__(256) void k_check_states(SceneDev sc, int64_t M, co
     }
 }
 
+// ---------------------------------------------------------------------------
+// Exact continuous edge check for a translating robot: the edge's time span
+// is cut where an obstacle changes segment; on each piece the robot (linear
+// along the edge) and the obstacle (one constant-velocity segment, or held)
+// move linearly, so a sphere pair's relative position is affine in time and
+// its closest approach is u* = clamp(-p0.(p1 - p0) / |p1 - p0|^2, 0, 1)
+// between the piece's end values.  The box and horizon hold along the edge
+// iff they hold at both endpoints (convex sets).  One thread per edge.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void obstacle_at(const float4 *lds, int n_seg, int o, int k, float t, float &x, float &y,
+                                            float &z) {
+    float nx, ny, nz;
+    obstacle_n(lds, n_seg, o, k, t, nx, ny, nz);
+    x = -0.5f * nx;
+    y = -0.5f * ny;
+    z = -0.5f * nz;
+}
+
+__global__ __launch_bounds__(256) void k_edge_continuous(SceneDev sc, int64_t E, const float *__restrict__ xa,
+                                                         const float *__restrict__ xb, uint8_t *__restrict__ free_out,
+                                                         float *__restrict__ dmin_out) {
+    extern __shared__ float4 lds[];
+    stage_obstacles(sc, lds);
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int d = sc.d, W = d + 1;
+    const float *A = xa + e * W, *B = xb + e * W;
+    if (A[d] > B[d]) { const float *tmp = A; A = B; B = tmp; }
+    float qa[3] = {0.f, 0.f, 0.f}, qb[3] = {0.f, 0.f, 0.f};
+    for (int j = 0; j < d && j < 3; ++j) {
+        qa[j] = A[j];
+        qb[j] = B[j];
+    }
+    bool ok = true;
+    for (int j = 0; j < d; ++j)
+        ok = ok && A[j] >= sc.q_lo[j] && A[j] <= sc.q_hi[j] && B[j] >= sc.q_lo[j] && B[j] <= sc.q_hi[j];
+    const float ta = A[d], tb = B[d], T = tb - ta;
+    ok = ok && ta >= 0.f && tb <= sc.H;
+    float best = INFINITY;
+    const float *lt = reinterpret_cast<const float *>(lds + sc.lds_t);
+    for (int o = 0; o < sc.O; ++o) {
+        const int ka = sc.obs_mode == kObsShared ? shared_segment(sc, ta) : generic_segment(sc, lds, o, ta);
+        const int kb = sc.obs_mode == kObsShared ? shared_segment(sc, tb) : generic_segment(sc, lds, o, tb);
+        for (int k = ka; k <= kb; ++k) {
+            const float tk1 = sc.obs_mode == kObsShared ? sc.seg_t[k + 1] : lt[o * (sc.n_seg + 1) + k + 1];
+            const float t0 = k == ka ? ta : lds[(o * sc.n_seg + k) * 2].w;
+            const float t1 = k == kb ? tb : tk1;
+            float c0x, c0y, c0z, c1x, c1y, c1z;
+            obstacle_at(lds, sc.n_seg, o, k, t0, c0x, c0y, c0z);
+            obstacle_at(lds, sc.n_seg, o, k, t1, c1x, c1y, c1z);
+            const float f0 = T > 0.f ? (t0 - ta) / T : 0.f, f1 = T > 0.f ? (t1 - ta) / T : 0.f;
+            float r0[3], r1[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                r0[c] = fmaf(f0, qb[c] - qa[c], qa[c]);
+                r1[c] = fmaf(f1, qb[c] - qa[c], qa[c]);
+            }
+            for (int s = 0; s < sc.S; ++s) {
+                const float4 sp = lds[sc.lds_sph + s];
+                const float p0x = r0[0] + sp.x - c0x, p0y = r0[1] + sp.y - c0y, p0z = r0[2] + sp.z - c0z;
+                const float dx = (r1[0] + sp.x - c1x) - p0x, dy = (r1[1] + sp.y - c1y) - p0y,
+                            dz = (r1[2] + sp.z - c1z) - p0z;
+                const float pp = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                const float pd = fmaf(p0x, dx, fmaf(p0y, dy, p0z * dz));
+                const float u = pp > 0.f ? fminf(fmaxf(-pd / pp, 0.f), 1.f) : 0.f;
+                const float mx = fmaf(u, dx, p0x), my = fmaf(u, dy, p0y), mz = fmaf(u, dz, p0z);
+                const float dist = sqrtf(fmaf(mx, mx, fmaf(my, my, mz * mz))) - (sp.w + sc.obs_r[o]);
+                best = fminf(best, dist);
+            }
+        }
+    }
+    free_out[e] = ok && best >= 0.f ? 1 : 0;
+    if (dmin_out) dmin_out[e] = best;
+}
+
+hipError_t launch_check_edges_continuous(const SceneDev &sc, int64_t E, const float *xa, const float *xb,
+                                         uint8_t *free_out, float *dmin_out, hipStream_t s) {
+    if (E <= 0) return hipSuccess;
+    k_edge_continuous<<<(int)((E + 255) / 256), 256, scene_lds_bytes(sc), s>>>(sc, E, xa, xb, free_out, dmin_out);
+    return hipGetLastError();
+}
+
 // World centres of the robot's spheres at q_g (one thread per sphere, the
 // same kinematics code as the state tests, so the goal-state tests decide
 // exactly as a state test at q = q_g would).

@@ -45,6 +45,7 @@ struct SceneDev {
     int lds_goal;               // float4 offset in LDS of the sphere centres at q_g
     const float4 *sph;          // [S]
     const float4 *goal;         // [S] world centres at q_g (x, y, z, |c|^2)
+    const float *obs_r;         // [O] obstacle radii (the continuous check)
     const float *R2;            // [S][O_pad]
     const float4 *seg;          // [O_pad][n_seg][2]
     const float *seg_t;         // shared mode: [n_seg+1]; generic: [O_pad][n_seg+1]

@@ -158,6 +158,7 @@ struct st_problem {
     float *d_R2 = nullptr;
     float4 *d_seg = nullptr;
     float4 *d_goal = nullptr;  // sphere centres at q_g
+    float *d_obs_r = nullptr;  // obstacle radii
     float *d_segt = nullptr;
     // goal grid and windows
     int64_t k_lo = 0, k_hi = -1;
@@ -196,6 +197,9 @@ namespace st {
 
 // ---- collision ------------------------------------------------------------
 size_t scene_lds_bytes(const SceneDev &sc);
+// Exact continuous edge check (translating robots); dmin_out may be null.
+hipError_t launch_check_edges_continuous(const SceneDev &sc, int64_t E, const float *xa, const float *xb,
+                                         uint8_t *free_out, float *dmin_out, hipStream_t s);
 // World centres (x, y, z, |c|^2) of the robot's spheres at q_g.
 hipError_t launch_goal_centers(const SceneDev &sc, float4 *out);
 hipError_t launch_check_states(const SceneDev &sc, int64_t M, const float *x, uint8_t *free_out, hipStream_t s);

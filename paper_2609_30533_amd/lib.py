@@ -83,6 +83,7 @@ class Info(C.Structure):
 # Every symbol the header declares (used by the load test).
 EXPORTS = [
     "st_problem_create", "st_problem_destroy", "st_problem_reset", "st_check_states", "st_check_edges",
+    "st_check_edges_continuous",
     "st_nearest", "st_sample_batch", "st_extend_batch", "st_iterate", "st_plan", "st_path_free", "st_get_info",
     "st_tree_export", "st_tree_import", "st_slots_export", "st_goal_grid_export", "st_partition_export",
     "st_set_tuning", "st_set_state_split", "st_set_flat_extension", "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
@@ -137,6 +138,7 @@ def load():
     L.st_last_error.argtypes = []
     L.st_last_error.restype = C.c_char_p
     L.st_path_get.argtypes = [vp, C.POINTER(Path)]
+    L.st_check_edges_continuous.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.st_batch_create.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp)]
     L.st_batch_destroy.argtypes = [vp]
     L.st_batch_destroy.restype = None
@@ -249,6 +251,16 @@ class Problem:
         _check(self.L.st_check_edges(self.h, E, _dptr(xa), _dptr(xb), _dptr(free), _dptr(fh), _stream(stream)),
                "st_check_edges")
         return free, fh
+
+    def check_edges_continuous(self, xa, xb, stream=None):
+        """Exact continuous check (translating robots): (free, least clearance)."""
+        import torch
+        E = xa.shape[0]
+        free = torch.empty(E, dtype=torch.uint8, device=xa.device)
+        dmin = torch.empty(E, dtype=torch.float32, device=xa.device)
+        _check(self.L.st_check_edges_continuous(self.h, E, _dptr(xa), _dptr(xb), _dptr(free), _dptr(dmin),
+                                                _stream(stream)), "st_check_edges_continuous")
+        return free, dmin
 
     # ---- nearest ------------------------------------------------------------
     def nearest(self, xq, set_id=SET_FORWARD, metric=METRIC_RHO, sigma=1, stream=None):

@@ -186,3 +186,37 @@ def test_full_size_sampled(oracle_lib):
     assert np.array_equal(free[pick][ok], orc["free"][ok])
     assert np.array_equal(fh[pick][ok], orc["first_hit"][ok])
     assert 0.05 < free.mean() < 0.95
+
+
+@pytest.mark.parametrize("piecewise", [False, True], ids=["constant-velocity", "piecewise"])
+def test_continuous_check_matches_oracle(oracle_lib, piecewise):
+    """The exact continuous check against the oracle's closed form: free flags
+    bit-exact wherever the clearance is not within 1e-4 of contact, least
+    clearance within 1e-5."""
+    from paper_2609_30533_amd.lib import Problem
+    from tests.test_oracle_geometry import _piecewise_disc
+    prob = _piecewise_disc(8) if piecewise else scenes.disc2d(5)
+    banner("continuous %s" % ("piecewise" if piecewise else "linear"))
+    xa, xb = scenes.synthetic_edges(prob, 3000, seed=15, bridge_mix=True)
+    gp = Problem(prob)
+    f, dm = gp.check_edges_continuous(to_dev(xa), to_dev(xb))
+    f, dm = f.cpu().numpy(), dm.cpu().numpy()
+    o = oracle_lib.Oracle(prob)
+    n_free = n_hit = 0
+    for e in range(len(xa)):
+        ok, m = o.edge_continuous_pw(xa[e].astype(np.float64), xb[e].astype(np.float64))
+        assert abs(dm[e] - m) <= 1e-5 * max(1.0, abs(m)), (e, dm[e], m)
+        if abs(m) > MARGIN:
+            assert bool(f[e]) == ok, (e, f[e], ok, m)
+            n_free += ok
+            n_hit += not ok
+    assert n_free > 200 and n_hit > 200
+
+
+def test_continuous_check_rejects_arms():
+    from paper_2609_30533_amd.lib import Problem, StError
+    prob = scenes.arm6(1)
+    gp = Problem(prob)
+    x = to_dev(np.zeros((4, 7), dtype=np.float32))
+    with pytest.raises(StError):
+        gp.check_edges_continuous(x, x)

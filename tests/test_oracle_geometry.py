@@ -195,6 +195,75 @@ def test_discrete_check_converges_to_continuous(oracle_lib):
     del rng
 
 
+def _piecewise_disc(seed, n_wp=5):
+    """disc2d scene whose obstacles follow random 5-waypoint paths."""
+    prob = scenes.disc2d(seed)
+    rng = np.random.default_rng([7, seed])
+    O = prob.n_obs
+    wp = np.zeros((O, n_wp, 4))
+    times = np.sort(np.r_[0.0, rng.uniform(0.5, 9.5, size=n_wp - 2), 10.0])
+    for o in range(O):
+        wp[o, :, 0] = times
+        wp[o, :, 1:3] = rng.uniform(0.0, 1.0, size=(n_wp, 2))
+    prob.wp = scenes.f32(wp)
+    prob.n_wp = np.full(O, n_wp, dtype=np.int32)
+    return prob
+
+
+def _sampled_clearance(prob, a, b, n=20001):
+    """Brute force: least pair clearance over n evenly spaced times of the
+    edge, obstacle positions by linear interpolation of the waypoints."""
+    if a[-1] > b[-1]:
+        a, b = b, a
+    ts = np.linspace(a[-1], b[-1], n)
+    f = (ts - a[-1]) / (b[-1] - a[-1]) if b[-1] > a[-1] else np.zeros(n)
+    rx = a[0] + f * (b[0] - a[0]) + prob.sphere[0, 0]
+    ry = a[1] + f * (b[1] - a[1]) + prob.sphere[0, 1]
+    best = np.inf
+    for o in range(prob.n_obs):
+        w = prob.wp[o, :prob.n_wp[o]]
+        ox = np.interp(ts, w[:, 0], w[:, 1])
+        oy = np.interp(ts, w[:, 0], w[:, 2])
+        oz = np.interp(ts, w[:, 0], w[:, 3])
+        dist = np.sqrt((rx - ox) ** 2 + (ry - oy) ** 2 + oz ** 2) - (prob.sphere[0, 3] + prob.obs_r[o])
+        best = min(best, dist.min())
+    return best
+
+
+def test_piecewise_continuous_check(oracle_lib):
+    """The closed-form check with trajectories cut at their waypoints: equal to
+    the single-segment form on constant-velocity scenes; on piecewise scenes
+    never above a dense brute-force sampling of the same motion and within
+    the sampling resolution of it; consistent with the discrete check (free
+    continuously implies free discretely, a discrete hit implies a
+    continuous one)."""
+    prob = scenes.disc2d(5)
+    o = oracle_lib.Oracle(prob)
+    xa, xb = scenes.synthetic_edges(prob, 500, seed=13, bridge_mix=True)
+    for e in range(len(xa)):
+        ok1, d1 = o.edge_continuous(xa[e], xb[e])
+        ok2, d2 = o.edge_continuous_pw(xa[e], xb[e])
+        assert abs(d1 - d2) < 1e-12 and ok1 == ok2
+    pw = _piecewise_disc(8)
+    op = oracle_lib.Oracle(pw)
+    xa, xb = scenes.synthetic_edges(pw, 400, seed=14, bridge_mix=True)
+    xa, xb = xa.astype(np.float64), xb.astype(np.float64)
+    res = op.check_edges(xa, xb)
+    n_free = n_hit = 0
+    for e in range(len(xa)):
+        ok, dm = op.edge_continuous_pw(xa[e], xb[e])
+        ds = _sampled_clearance(pw, xa[e], xb[e])
+        assert ds >= dm - 1e-9, (e, ds, dm)
+        assert ds - dm <= 2e-4, (e, ds, dm)
+        if ok:
+            assert res["free"][e] == 1
+            n_free += 1
+        if res["free"][e] == 0:
+            assert not ok
+            n_hit += 1
+    assert n_free > 50 and n_hit > 50
+
+
 def test_edge_check_brute_force_tiny(oracle_lib):
     """Every state x every pair, no early exit, enumerated independently."""
     prob = scenes.arm6(4, n_obs=2, n_wp=3)
