@@ -264,6 +264,19 @@ int st_plan(st_problem *p, const st_budget *budget, st_path *out);
 
 void st_path_free(st_path *path);
 
+/* A goal sequence (Sec. III: q_g^1, ..., q_g^m visited in order), planned as
+ * successive single-goal queries: query i starts at the previous goal with
+ * local time 0, the obstacle trajectories shifted by the previous arrival
+ * and the remaining horizon; only the last goal keeps the arrival range's
+ * lower end.  desc gives the robot, the start, the obstacles, the horizon and
+ * the parameters (desc->q_goal is ignored); goals: host [m][d].  Each query
+ * gets the budget.  out: the whole path in absolute time (host,
+ * library-allocated, st_path_free), arrival T_m and total length.  Returns
+ * ST_OK or ST_NO_SOLUTION (some query failed; out holds no states).
+ * Synchronous. */
+int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals, const st_budget *budget,
+                     st_path *out);
+
 /* The current incumbent path of a problem (host, library-allocated; free with
  * st_path_free).  Returns ST_OK or ST_NO_SOLUTION.  Synchronous. */
 int st_path_get(st_problem *p, st_path *out);

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <numeric>
 
 #include "st_internal.hpp"
@@ -580,6 +581,88 @@ int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, u
     if (rc != ST_OK) return rc;
     ST_HIP(launch_check_edges(p->sc, p->ebufs_api, E, xa, xb, nullptr, free_out, first_hit, p->tune_api,
                               (hipStream_t)stream, nullptr, split_for(p->split_api, E)));
+    return ST_OK;
+}
+
+int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals, const st_budget *budget,
+                     st_path *out) {
+    if (!desc || m < 1 || !goals || !budget || !out) return fail(ST_EINVAL, "st_plan_sequence: bad arguments");
+    memset(out, 0, sizeof *out);
+    const int d = desc->dof;
+    out->dof = d;
+    out->first_solution_iter = -1;
+    out->arrival = INFINITY;
+    out->length = INFINITY;
+    const auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    const int O = desc->n_obstacles, Wm = desc->max_waypoints;
+    std::vector<double> wp(O > 0 ? (size_t)O * Wm * 4 : 1);
+    std::vector<double> qs(desc->q_start, desc->q_start + d);
+    std::vector<double> states;  // absolute-time path, rows of d + 1
+    double T = 0.0, C = 0.0;
+    int64_t iters = 0;
+    int rc = ST_OK;
+    for (int i = 0; i < m && rc == ST_OK; ++i) {
+        // leg i: local time 0 at the previous arrival, obstacles shifted by it,
+        // the remaining horizon; only the last goal keeps the arrival range's
+        // lower end
+        st_problem_desc D = *desc;
+        for (int o = 0; o < O; ++o)
+            for (int k = 0; k < Wm; ++k) {
+                const size_t r = ((size_t)o * Wm + k) * 4;
+                wp[r] = desc->waypoints[r] - T;
+                for (int c = 1; c < 4; ++c) wp[r + c] = desc->waypoints[r + c];
+            }
+        if (O > 0) D.waypoints = wp.data();
+        D.q_start = qs.data();
+        D.q_goal = goals + (size_t)i * d;
+        D.t_max = desc->t_max - T;
+        D.t_min = i + 1 == m ? std::max(0.0, desc->t_min - T) : 0.0;
+        D.params.problem_id = desc->params.problem_id + 7919u * (uint32_t)i;
+        if (!(D.t_max > 0.0)) {
+            rc = ST_NO_SOLUTION;
+            break;
+        }
+        st_problem *p = nullptr;
+        if ((rc = st_problem_create(&D, &p)) != ST_OK) break;
+        st_path leg;
+        const int lr = st_plan(p, budget, &leg);
+        st_problem_destroy(p);
+        if (lr < 0) {
+            rc = lr;
+            break;
+        }
+        if (lr == ST_NO_SOLUTION || leg.n_states < 1) {
+            st_path_free(&leg);
+            rc = ST_NO_SOLUTION;
+            break;
+        }
+        // append in absolute time; a leg starts where the previous one ended
+        for (int64_t s = (i > 0 ? 1 : 0); s < leg.n_states; ++s) {
+            for (int j = 0; j < d; ++j) states.push_back(leg.states[s * (d + 1) + j]);
+            states.push_back(leg.states[s * (d + 1) + d] + T);
+        }
+        T += leg.arrival;
+        C += leg.length;
+        iters += leg.iterations;
+        if (i + 1 == m) {
+            out->first_solution_iter = leg.first_solution_iter;
+            out->first_solution_ms = ms_since() - (leg.total_ms - leg.first_solution_ms);
+        }
+        st_path_free(&leg);
+        qs.assign(goals + (size_t)i * d, goals + (size_t)(i + 1) * d);
+    }
+    out->iterations = iters;
+    out->total_ms = ms_since();
+    if (rc != ST_OK) return rc;
+    out->n_states = (int64_t)(states.size() / (d + 1));
+    out->states = (double *)malloc(sizeof(double) * states.size());
+    if (!out->states) return fail(ST_ENOMEM, "st_plan_sequence: out of host memory");
+    memcpy(out->states, states.data(), sizeof(double) * states.size());
+    out->arrival = T;
+    out->length = C;
     return ST_OK;
 }
 

@@ -89,7 +89,7 @@ EXPORTS = [
     "st_set_tuning", "st_set_state_split", "st_set_flat_extension", "st_profile_enable", "st_profile_read", "st_work_counters", "st_last_error",
     "st_mlp_create", "st_mlp_destroy", "st_mlp_param_count", "st_mlp_params", "st_mlp_grads", "st_mlp_forward",
     "st_mlp_loss", "st_mlp_backward", "st_mlp_adam", "st_proposal_set",
-    "st_path_get", "st_batch_create", "st_batch_destroy", "st_batch_iterate", "st_batch_plan",
+    "st_path_get", "st_plan_sequence", "st_batch_create", "st_batch_destroy", "st_batch_iterate", "st_batch_plan",
 ]
 NO_INT_RESULT = ("st_problem_destroy", "st_path_free", "st_last_error", "st_mlp_destroy", "st_mlp_param_count",
                  "st_batch_destroy")
@@ -138,6 +138,7 @@ def load():
     L.st_last_error.argtypes = []
     L.st_last_error.restype = C.c_char_p
     L.st_path_get.argtypes = [vp, C.POINTER(Path)]
+    L.st_plan_sequence.argtypes = [C.POINTER(Desc), i32, C.POINTER(C.c_double), C.POINTER(Budget), C.POINTER(Path)]
     L.st_check_edges_continuous.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.st_batch_create.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp)]
     L.st_batch_destroy.argtypes = [vp]
@@ -187,6 +188,56 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def make_desc(prob: scenes.Problem, problem_id: int = 0):
+    """st_problem_desc for a generated problem; returns (desc, arrays to keep alive)."""
+    keep = []
+
+    def arr(a, dt):
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data_as(C.POINTER(C.c_double if dt == np.float64 else C.c_int32))
+
+    D = Desc()
+    D.dof, D.robot_kind = prob.d, prob.kind
+    D.dh = arr(prob.dh, np.float64)
+    D.n_spheres = prob.n_spheres
+    D.sphere_link = arr(prob.sphere_link, np.int32)
+    D.spheres = arr(prob.sphere, np.float64)
+    D.q_lo, D.q_hi = arr(prob.q_lo, np.float64), arr(prob.q_hi, np.float64)
+    D.q_start, D.q_goal = arr(prob.q_start, np.float64), arr(prob.q_goal, np.float64)
+    D.t_min, D.t_max, D.v_max = prob.t_min, prob.t_max, prob.v_max
+    D.n_obstacles, D.max_waypoints = prob.n_obs, max(prob.w_max, 1)
+    D.n_waypoints = arr(prob.n_wp, np.int32)
+    D.waypoints = arr(prob.wp, np.float64)
+    D.obstacle_radius = arr(prob.obs_r, np.float64)
+    p = prob.params
+    D.params = Params(p.variant, p.n_groups, p.batch, p.eta, p.h, p.dt, p.p_new, p.p_guided, p.cap_fwd,
+                      p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF,
+                      1 if getattr(p, "no_recycling", 0) else 0)
+    return D, keep
+
+
+def plan_sequence(prob: scenes.Problem, goals, max_iters=0, max_ms=0.0, stop_at_first=False, iters_per_sync=0,
+                  problem_id: int = 0):
+    """st_plan_sequence: visit goals [m][d] in order from prob's start."""
+    L = load()
+    D, keep = make_desc(prob, problem_id)
+    g = np.ascontiguousarray(goals, dtype=np.float64)
+    b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
+    path = Path()
+    rc = _check(L.st_plan_sequence(C.byref(D), int(g.shape[0]), g.ctypes.data_as(C.POINTER(C.c_double)),
+                                   C.byref(b), C.byref(path)), "st_plan_sequence")
+    try:
+        n = path.n_states
+        d = prob.d
+        states = np.ctypeslib.as_array(path.states, shape=(n * (d + 1),)).reshape(n, d + 1).copy() if n > 0 else None
+        return dict(rc=rc, states=states, U=path.arrival, C=path.length, iterations=path.iterations,
+                    first_ms=path.first_solution_ms, total_ms=path.total_ms)
+    finally:
+        L.st_path_free(C.byref(path))
+        del keep
+
+
 class Problem:
     """One planning problem on the current HIP device."""
 
@@ -195,30 +246,7 @@ class Problem:
         self.prob = prob
         self.d = prob.d
         self.N = prob.params.n_groups
-        keep = []
-
-        def arr(a, dt):
-            a = np.ascontiguousarray(a, dtype=dt)
-            keep.append(a)
-            return a.ctypes.data_as(C.POINTER(C.c_double if dt == np.float64 else C.c_int32))
-
-        D = Desc()
-        D.dof, D.robot_kind = prob.d, prob.kind
-        D.dh = arr(prob.dh, np.float64)
-        D.n_spheres = prob.n_spheres
-        D.sphere_link = arr(prob.sphere_link, np.int32)
-        D.spheres = arr(prob.sphere, np.float64)
-        D.q_lo, D.q_hi = arr(prob.q_lo, np.float64), arr(prob.q_hi, np.float64)
-        D.q_start, D.q_goal = arr(prob.q_start, np.float64), arr(prob.q_goal, np.float64)
-        D.t_min, D.t_max, D.v_max = prob.t_min, prob.t_max, prob.v_max
-        D.n_obstacles, D.max_waypoints = prob.n_obs, max(prob.w_max, 1)
-        D.n_waypoints = arr(prob.n_wp, np.int32)
-        D.waypoints = arr(prob.wp, np.float64)
-        D.obstacle_radius = arr(prob.obs_r, np.float64)
-        p = prob.params
-        D.params = Params(p.variant, p.n_groups, p.batch, p.eta, p.h, p.dt, p.p_new, p.p_guided, p.cap_fwd,
-                          p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF,
-                          1 if getattr(p, "no_recycling", 0) else 0)
+        D, keep = make_desc(prob, problem_id)
         h = C.c_void_p()
         _check(self.L.st_problem_create(C.byref(D), C.byref(h)), "st_problem_create")
         self.h = h
