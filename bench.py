@@ -30,6 +30,11 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3      # MI355X published vector FP32 peak
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per edge-check launch (average of an extension and a bridge launch)
+# from the FETCH_SIZE / WRITE_SIZE profiles of the current kernels, scaled by a
+# plain copy kernel of known size (profiles/traffic_arm6_single.md); to be
+# measured again whenever the edge-check kernels change.
+EDGE_LAUNCH_HBM_BYTES = 1.6205e6
 
 
 def flops_per_state(prob) -> int:
@@ -303,6 +308,9 @@ def main():
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0,
+                    help="only copy this many MiB device to device three times (the reference kernel that "
+                         "scales the memory counters of a profile) and exit")
     ap.add_argument("--ablation", type=int, default=0,
                     help="only run the recycling ablation on this many problems per condition and print JSON")
     ap.add_argument("--ablation-ms", type=float, default=1000.0)
@@ -319,6 +327,16 @@ def main():
     from paper_2609_30533_amd import lib, scenes
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     torch.cuda.init()
+
+    if args.copy_reference > 0:
+        n = args.copy_reference * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": n * 4, "copies": 3}))
+        return
 
     if args.ablation > 0:
         for r in ablation(lib, scenes, args):
@@ -390,7 +408,8 @@ def main():
                                "interval root N=8, B=4096, h=0.02 rad, eta=0.5",
                    "problem_seed": seed, "batch": prob.params.batch, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                     "frac": achieved / PEAK_FP32_TFLOPS, "traffic": EDGE_LAUNCH_HBM_BYTES,
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x 2.0 + WRITE_SIZE, copy-scaled)",
                      "kernel": "k_check_edges (extension + bridge launches)",
                      "flops_per_state": W, "states": states, "launches": launches,
                      "avg_launch_ms": ms_edge / max(launches, 1),

@@ -295,7 +295,9 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
             const bool hit = state_hits<KIND, OT, OBS, true, SPLIT>(sc, lds, q, t, act, group_mask, lower_mask, part);
             const uint64_t hm = __ballot(hit && act) & group_mask;
             if (!done && hm) {
-                atomicMin(&eb.hit[e], (int32_t)(c * ls + ((__builtin_ctzll(hm) - gsel * lpe) / SPLIT)));
+                // one atomic per group: its lowest hitting lane
+                if (lane == __builtin_ctzll(hm))
+                    atomicMin(&eb.hit[e], (int32_t)(c * ls + ((__builtin_ctzll(hm) - gsel * lpe) / SPLIT)));
                 done = true;
             }
             if (__ballot(!done) == 0) break;
