@@ -31,7 +31,7 @@
 namespace st {
 
 constexpr int kTileQ = 256;  // queries per scan tile (one per thread)
-constexpr int kMaxNch = 64;
+constexpr int kMaxNch = 256;  // node slices per scan tile at most
 constexpr unsigned long long kNoKey = ~0ull;
 constexpr int kSetAllBackward = -2;
 
@@ -399,9 +399,9 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     __syncthreads();
     const int np = s_np;
     const int64_t total = s_pre[np];
-    const int64_t c0 = (int64_t)blockIdx.y * total / a.nch, c1 = (int64_t)(blockIdx.y + 1) * total / a.nch;
     const bool act = tid < n;
     const int q = act ? (a.order ? a.order[tile.y + tid] : tile.y + tid) : 0;
+    const int64_t c0 = (int64_t)blockIdx.y * total / a.nch, c1 = (int64_t)(blockIdx.y + 1) * total / a.nch;
     float qx[kMaxDof];
     float aq = 0.f;
 #pragma unroll
@@ -702,7 +702,7 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
 template <bool MULTI>
 __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const BridgeArgs *av) {
     const BridgeArgs &a = MULTI ? av[blockIdx.y] : a0;
-    // one wave per worker: lane y reads the y-th slice's best candidate
+    // one wave per worker: lane y reads slices y, y + 64, ... and keeps the best
     const int lane = threadIdx.x & 63;
     const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     if (w >= a.B) return;
@@ -711,11 +711,15 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
     const bool adv = k.status[w] == ST_STATUS_ADVANCED;
     unsigned long long bk = kNoKey;
     uint32_t bi = 0xffffffffu;
-    if (adv && lane < a.nch) {
-        const int32_t ii = k.br_idx[(int64_t)lane * a.B + w];
-        if (ii >= 0) {
-            bk = k.br_key[(int64_t)lane * a.B + w];
-            bi = (uint32_t)ii;
+    if (adv) {
+        for (int y = lane; y < a.nch; y += 64) {
+            const int32_t ii = k.br_idx[(int64_t)y * a.B + w];
+            if (ii < 0) continue;
+            const unsigned long long kk = k.br_key[(int64_t)y * a.B + w];
+            if (kk < bk || (kk == bk && (uint32_t)ii < bi)) {
+                bk = kk;
+                bi = (uint32_t)ii;
+            }
         }
     }
     // lexicographic (key, index) minimum over the wave
@@ -1136,9 +1140,12 @@ int work_reserve(st_problem *p, int64_t B) {
     return ST_OK;
 }
 
-// Node slices per tile: enough blocks to fill the 256 CUs a few times over.
-static int nch_for(int tiles) {
-    int n = 1024 / std::max(tiles, 1);
+// Node slices per tile: about `blocks` scan blocks in all.  More slices cut
+// the nodes one thread walks (the latency of a scan of a large tree) but
+// add partial results: the nearest-node scan merges them with 64-bit atomics
+// (one per query and slice), the bridge scan with a per-worker reduction.
+static int nch_for(int tiles, int blocks = 1024) {
+    int n = blocks / std::max(tiles, 1);
     return std::max(1, std::min(kMaxNch, n));
 }
 int nch_for_tiles(int tiles) { return nch_for(tiles); }
@@ -1310,7 +1317,8 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
         if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
     }
     IterArgs a;
-    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools)), nch_for(max_tiles(B, 2)), 1024, B, a);
+    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools), 4096), nch_for(max_tiles(B, 2), 4096), 1024,
+                   B, a);
     const int blocks = (int)((B + 255) / 256);
     prof_mark(p, kStNearest, s);
     k_prep<false><<<1, 1024, 0, s>>>(a.prep_nn, nullptr);
