@@ -447,6 +447,8 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
         if (c + kTileQ < c1) fetch(c + kTileQ);
         const int m = (int)min<int64_t>(kTileQ, c1 - c);
         if (act) {
+            // unrolled so that the LDS reads of several nodes are in flight together
+#pragma unroll 8
             for (int k = 0; k < m; ++k) {
                 float D2 = 0.f;
 #pragma unroll
