@@ -12,6 +12,7 @@ _SRC = os.path.join(_HERE, "st_oracle.c")
 _BUILD = os.path.join(_HERE, "_build")
 
 MAX_DOF, MAX_SPH, MAX_OBS, MAX_WP = 7, 128, 64, 32
+MAX_SELF, MAX_BOX = 32, 16
 
 
 def lib_path() -> str:
@@ -50,6 +51,8 @@ class Scene(C.Structure):
         ("p_new", C.c_double), ("p_guided", C.c_double),
         ("cap_fwd", C.c_int32), ("cap_bwd", C.c_int32),
         ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("no_recycling", C.c_int32),
+        ("n_self", C.c_int32), ("self_pair", C.c_int32 * 2 * MAX_SELF),
+        ("n_box", C.c_int32), ("box", C.c_double * 15 * MAX_BOX),
     ]
 
 
@@ -167,6 +170,16 @@ def make_scene(prob, problem_id: int = 0) -> Scene:
     s.cap_fwd, s.cap_bwd = p.cap_fwd, p.cap_bwd
     s.seed, s.problem_id = p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF
     s.no_recycling = 1 if getattr(p, "no_recycling", 0) else 0
+    pairs = np.asarray(getattr(prob, "self_pairs", np.zeros((0, 2))), dtype=np.int64).reshape(-1, 2)
+    boxes = np.asarray(getattr(prob, "boxes", np.zeros((0, 15))), dtype=np.float64).reshape(-1, 15)
+    assert len(pairs) <= MAX_SELF and len(boxes) <= MAX_BOX
+    s.n_self = len(pairs)
+    for k, (a, b) in enumerate(pairs):
+        s.self_pair[k][0], s.self_pair[k][1] = int(a), int(b)
+    s.n_box = len(boxes)
+    for k in range(len(boxes)):
+        for j in range(15):
+            s.box[k][j] = float(boxes[k, j])
     return s
 
 

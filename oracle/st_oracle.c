@@ -181,10 +181,27 @@ void orc_obstacle_pos(const orc_scene *sc, int o, double t, double *out) {
 /* State and edge validity.                                                  */
 /* ========================================================================= */
 
+/* Distance from point c to a closed oriented box: in the box's axes the
+ * offset u_a = axis_a . (c - centre); the excess over the half extent,
+ * max(|u_a| - h_a, 0), is the offset to the nearest box point along that
+ * axis, so the distance is the norm of the three excesses (0 inside). */
+static double box_distance(const double *B, const double *c) {
+    double e2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double *ax = B + 6 + 3 * a;
+        double u = ax[0] * (c[0] - B[0]) + ax[1] * (c[1] - B[1]) + ax[2] * (c[2] - B[2]);
+        double ex = fabs(u) - B[3 + a];
+        if (ex > 0.0) e2 += ex * ex;
+    }
+    return sqrt(e2);
+}
+
 /* valid(q,t) <=> q in C, 0 <= t <= H, and every robot sphere / obstacle pair
  * is at least r_s + r_o apart (touching counts as free; Eq. 1 with the
- * sphere model).  margin receives the least signed clearance: min over pairs
- * of |c_s - c_o| - r_s - r_o, and the distance to the box bounds. */
+ * sphere model).  With static geometry, also every robot sphere is at least
+ * its radius from every box, and every sphere pair of a listed link pair is
+ * at least r_s + r_s' apart.  margin receives the least signed clearance over
+ * all these pairs, and the distance to the box bounds. */
 int orc_state_valid(const orc_scene *sc, const double *x, double *margin) {
     int d = sc->d;
     double t = x[d];
@@ -213,6 +230,27 @@ int orc_state_valid(const orc_scene *sc, const double *x, double *margin) {
             double R = sc->sph[s][3] + sc->obs_r[o];
             if (dist < R) ok = 0;
             m = fmin(m, dist - R);
+        }
+    }
+    for (int b = 0; b < sc->n_box; ++b)
+        for (int s = 0; s < sc->n_sph; ++s) {
+            double dist = box_distance(sc->box[b], cs + 3 * s);
+            double R = sc->sph[s][3];
+            if (dist < R) ok = 0;
+            m = fmin(m, dist - R);
+        }
+    for (int k = 0; k < sc->n_self; ++k) {
+        int la = sc->self_pair[k][0], lb = sc->self_pair[k][1];
+        for (int s = 0; s < sc->n_sph; ++s) {
+            if (sc->sph_link[s] != la) continue;
+            for (int u = 0; u < sc->n_sph; ++u) {
+                if (sc->sph_link[u] != lb) continue;
+                double dx = cs[3 * s] - cs[3 * u], dy = cs[3 * s + 1] - cs[3 * u + 1], dz = cs[3 * s + 2] - cs[3 * u + 2];
+                double dist = sqrt(dx * dx + dy * dy + dz * dz);
+                double R = sc->sph[s][3] + sc->sph[u][3];
+                if (dist < R) ok = 0;
+                m = fmin(m, dist - R);
+            }
         }
     }
     if (margin) *margin = m;
@@ -275,7 +313,8 @@ void orc_check_states(const orc_scene *sc, int64_t M, const double *x, uint8_t *
  * against obstacles on a single constant-velocity segment over the edge's time
  * span: the relative position p(tau) = p0 + w tau is linear, its closest
  * approach is at tau* = clamp(-p0.w / |w|^2, 0, T).  Returns 1 when every
- * pair stays at distance >= R, and the least (distance - R) in dmin. */
+ * pair stays at distance >= R, and the least (distance - R) in dmin.  Only
+ * the moving obstacles enter (static boxes and link pairs belong to arms). */
 int orc_edge_continuous(const orc_scene *sc, const double *xa_in, const double *xb_in, double *dmin) {
     int d = sc->d;
     const double *xa = xa_in, *xb = xb_in;
@@ -320,7 +359,8 @@ int orc_edge_continuous(const orc_scene *sc, const double *xa_in, const double *
  * u* = clamp(-p0.(p1-p0) / |p1-p0|^2, 0, 1) between the piece's end values.
  * The box and horizon hold along the edge iff they hold at both endpoints
  * (convex sets).  Free iff they hold and every pair keeps distance >= R
- * (touching is free); dmin receives the least pair clearance. */
+ * (touching is free); dmin receives the least pair clearance.  Only the
+ * moving obstacles enter (static boxes and link pairs belong to arms). */
 int orc_edge_continuous_pw(const orc_scene *sc, const double *xa_in, const double *xb_in, double *dmin) {
     const int d = sc->d;
     const double *xa = xa_in, *xb = xb_in;

@@ -13,7 +13,9 @@
  *   Sec. IV-B (Eq. 5-7)  goal-time bound, guided windows, N groups, conditional
  *                        query time, directed space-time distance, Alg. 1 / 2
  *   Sec. V   (Eq. 8)     root recycling, maximum-speed extension, Alg. 3
- *   Sec. VI              obstacles interpolated at absolute query times
+ *   Sec. VI              obstacles interpolated at absolute query times;
+ *                        the arm's own links and fixed boxes (pRRTC's sphere
+ *                        checker lineage) as time-independent terms
  *
  * Readings of passages the paper leaves open are listed at each function.
  */
@@ -30,6 +32,8 @@ extern "C" {
 #define ORC_MAX_SPH 128
 #define ORC_MAX_OBS 64
 #define ORC_MAX_WP 32
+#define ORC_MAX_SELF 32
+#define ORC_MAX_BOX 16
 
 enum { ORC_KIND_TRANSLATE = 0, ORC_KIND_DH = 1 };
 enum { ORC_IR = 0, ORC_RR = 1 };
@@ -59,6 +63,15 @@ typedef struct orc_scene {
     int32_t cap_fwd, cap_bwd;
     uint32_t seed, problem_id;
     int32_t no_recycling;               /* recycling variant: 1 = roots fixed, deactivation only (ablation) */
+    /* static geometry (arms): link pairs tested against each other, and
+     * fixed oriented boxes.  A pair (la, lb) tests every sphere of link la
+     * against every sphere of link lb.  A box row is centre (3), half
+     * extents (3), then its three unit axes in world coordinates (3 x 3,
+     * one axis per row). */
+    int32_t n_self;
+    int32_t self_pair[ORC_MAX_SELF][2];
+    int32_t n_box;
+    double box[ORC_MAX_BOX][15];
 } orc_scene;
 
 typedef struct orc_planner orc_planner;

@@ -87,6 +87,11 @@ class Problem:
     obs_r: np.ndarray         # (O,)
     params: Params = field(default_factory=Params)
     seed: int = 0
+    # static geometry of arms: link pairs (la, lb) whose spheres are tested
+    # against each other, and fixed oriented boxes, one row each: centre (3),
+    # half extents (3), unit box axes in world coordinates (3 x 3, row-major)
+    self_pairs: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), dtype=np.int32))
+    boxes: np.ndarray = field(default_factory=lambda: np.zeros((0, 15), dtype=np.float64))
 
     @property
     def n_spheres(self) -> int:
@@ -124,6 +129,32 @@ ARM7_DH = np.array([
     [0.0,      math.pi / 2, 0.384, 0.0],
     [0.088,    math.pi / 2, 0.0,   0.0],
     [0.0,      0.0,         0.107, 0.0],
+])
+
+
+# Self-collision link pairs.  Reading: the pairs at least two links apart
+# whose sphere models do not touch at q = 0 (pairs that touch in that pose,
+# and neighbouring links, which share a joint, are left out, as an
+# allowed-collision list built from the home pose would).
+UR5E_SELF_PAIRS = np.array([[1, 3], [1, 4], [1, 5], [1, 6], [2, 4], [2, 5], [2, 6], [3, 5], [3, 6], [4, 6]],
+                           dtype=np.int32)
+ARM7_SELF_PAIRS = np.array([[1, 4], [1, 5], [1, 6], [1, 7], [2, 4], [2, 5], [2, 6], [2, 7], [3, 6], [3, 7],
+                            [4, 6], [4, 7], [5, 7]], dtype=np.int32)
+
+
+def _box(centre, half, yaw=0.0):
+    """Box row: centre, half extents, unit axes (rows) after a turn about z."""
+    c, s = math.cos(yaw), math.sin(yaw)
+    axes = np.array([[c, s, 0.0], [-s, c, 0.0], [0.0, 0.0, 1.0]])
+    return np.concatenate([np.asarray(centre, dtype=np.float64), np.asarray(half, dtype=np.float64), axes.ravel()])
+
+
+# Static environment of the arm workloads with fixed geometry: a table whose
+# top lies 7 cm below the base frame (clear of the base spheres) and a post
+# turned 30 degrees about z beside the robot.
+STATIC_BOXES = np.stack([
+    _box([0.0, 0.0, -0.095], [0.9, 0.9, 0.025]),
+    _box([0.55, 0.25, 0.3], [0.05, 0.15, 0.3], yaw=math.pi / 6),
 ])
 
 
@@ -283,7 +314,28 @@ def mixed(seed: int) -> Problem:
     return arm7rr(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p)
 
 
-WORKLOADS = {"disc2d": disc2d, "arm6": arm6, "arm7rr": arm7rr, "mixed": mixed}
+def self_pairs_for(prob: Problem) -> np.ndarray:
+    """The self-collision link pairs of the problem's arm."""
+    if prob.kind != KIND_DH:
+        return np.zeros((0, 2), dtype=np.int32)
+    return {6: UR5E_SELF_PAIRS, 7: ARM7_SELF_PAIRS}[prob.d].copy()
+
+
+def with_static(prob: Problem, boxes: np.ndarray | None = None) -> Problem:
+    """The arm problem with self-collision and the static boxes switched on
+    (the moving obstacles, start and goal unchanged)."""
+    assert prob.kind == KIND_DH, "static geometry is defined for arms"
+    prob.self_pairs = self_pairs_for(prob)
+    prob.boxes = np.array(STATIC_BOXES if boxes is None else boxes, dtype=np.float64).reshape(-1, 15)
+    prob.name = prob.name + "-static"
+    return prob
+
+
+def arm6static(seed: int, **kw) -> Problem:
+    return with_static(arm6(seed, **kw))
+
+
+WORKLOADS = {"disc2d": disc2d, "arm6": arm6, "arm7rr": arm7rr, "mixed": mixed, "arm6static": arm6static}
 
 
 # ----------------------------------------------------------------------------
