@@ -35,6 +35,8 @@ extern "C" {
 #define ST_MAX_OBSTACLES 64
 #define ST_MAX_WAYPOINTS 32
 #define ST_MAX_GROUPS 128
+#define ST_MAX_SELF_PAIRS 32
+#define ST_MAX_BOXES 16
 
 /* return codes */
 #define ST_OK 0
@@ -114,6 +116,20 @@ typedef struct st_problem_desc {
     const double *waypoints;       /* [O][max_waypoints][4]: t, x, y, z (times non-decreasing) */
     const double *obstacle_radius; /* [O] */
     st_params params;
+    /* Static geometry of an arm (ST_ROBOT_DH only; zero counts switch it off).
+     * Time-independent terms of the state test, after the sphere checker the
+     * paper reuses (Sec. VI):
+     *  - self collision: pair k = (la, lb), 0 <= la < lb <= d, tests every
+     *    sphere of link la against every sphere of link lb (free iff at least
+     *    r_s + r_s' apart); duplicates are ignored;
+     *  - fixed oriented boxes: a sphere is free iff its centre is at least r_s
+     *    from the closed box. */
+    int32_t n_self_pairs;          /* 0..ST_MAX_SELF_PAIRS */
+    const int32_t *self_pairs;     /* [n_self_pairs][2] link indices */
+    int32_t n_boxes;               /* 0..ST_MAX_BOXES */
+    const double *boxes;           /* [n_boxes][15]: centre (3), half extents (3, >= 0), then the
+                                      three unit box axes in world coordinates, one per row
+                                      (orthonormal to 1e-6) */
 } st_problem_desc;
 
 typedef struct st_problem st_problem;
@@ -193,7 +209,8 @@ int st_problem_reset(st_problem *p);
 
 /* valid(q,t) for M states.  x: device [M][d+1]; free_out: device [M] (1 = free).
  * A state is free when q is inside C, 0 <= t <= H and every robot sphere is at
- * least r_s + r_o from every obstacle (touching is free). */
+ * least r_s + r_o from every obstacle (touching is free), and, with static
+ * geometry, the listed link pairs and the boxes are clear as well. */
 int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out, void *stream);
 
 /* Discretised edge validity ("collision-checked along their interpolations",

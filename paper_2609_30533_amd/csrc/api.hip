@@ -100,6 +100,30 @@ static int validate(const st_problem_desc *D) {
             }
         }
     }
+    if (D->n_self_pairs < 0 || D->n_self_pairs > ST_MAX_SELF_PAIRS)
+        return fail(ST_EINVAL, "n_self_pairs %d outside 0..%d", D->n_self_pairs, ST_MAX_SELF_PAIRS);
+    if (D->n_boxes < 0 || D->n_boxes > ST_MAX_BOXES) return fail(ST_EINVAL, "n_boxes %d outside 0..%d", D->n_boxes, ST_MAX_BOXES);
+    if ((D->n_self_pairs > 0 || D->n_boxes > 0) && D->robot_kind != ST_ROBOT_DH)
+        return fail(ST_EINVAL, "self pairs and boxes are defined for arms (ST_ROBOT_DH)");
+    if (D->n_self_pairs > 0 && !D->self_pairs) return fail(ST_EINVAL, "missing self pair array");
+    for (int k = 0; k < D->n_self_pairs; ++k) {
+        const int la = D->self_pairs[2 * k], lb = D->self_pairs[2 * k + 1];
+        if (la < 0 || la >= lb || lb > d) return fail(ST_EINVAL, "self pair %d = (%d, %d) needs 0 <= la < lb <= %d", k, la, lb, d);
+    }
+    if (D->n_boxes > 0 && !D->boxes) return fail(ST_EINVAL, "missing box array");
+    for (int b = 0; b < D->n_boxes; ++b) {
+        const double *B = D->boxes + 15 * b;
+        for (int c = 0; c < 15; ++c)
+            if (!finite(B[c])) return fail(ST_EINVAL, "box %d not finite", b);
+        for (int c = 3; c < 6; ++c)
+            if (B[c] < 0) return fail(ST_EINVAL, "box %d has a negative half extent", b);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const double *u = B + 6 + 3 * i, *v = B + 6 + 3 * j;
+                const double dot = u[0] * v[0] + u[1] * v[1] + u[2] * v[2];
+                if (fabs(dot - (i == j ? 1.0 : 0.0)) > 1e-6) return fail(ST_EINVAL, "box %d axes not orthonormal", b);
+            }
+    }
     const st_params &P = D->params;
     if (P.variant != ST_INTERVAL_ROOT && P.variant != ST_ROOT_RECYCLING) return fail(ST_EINVAL, "variant %d", P.variant);
     if (P.no_recycling != 0 && P.no_recycling != 1) return fail(ST_EINVAL, "no_recycling %d", P.no_recycling);
@@ -236,7 +260,12 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.lds_r2 = sc.lds_sph + S;
     sc.lds_t = sc.lds_r2 + (S * sc.O_pad + 3) / 4;
     sc.lds_goal = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));
-    sc.lds_f4 = sc.lds_goal + S;
+    sc.lds_box = sc.lds_goal + S;
+    sc.lds_f4 = sc.lds_box + 4 * D->n_boxes;
+    // static geometry: link-pair masks and boxes as (axis, -axis . centre) rows
+    sc.n_box = D->n_boxes;
+    for (int k = 0; k < D->n_self_pairs; ++k) sc.self_mask[D->self_pairs[2 * k + 1]] |= 1u << D->self_pairs[2 * k];
+    sc.stat = (D->n_self_pairs > 0 || D->n_boxes > 0) ? 1 : 0;
     int rc;
     if ((rc = dev_upload(&p->d_sph, sph.data(), sph.size())) != ST_OK) return rc;
     if ((rc = dev_upload(&p->d_R2, R2.data(), R2.size())) != ST_OK) return rc;
@@ -253,6 +282,20 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
         if ((rc = dev_upload(&p->d_obs_r, radii.data(), radii.size())) != ST_OK) return rc;
         sc.obs_r = p->d_obs_r;
     }
+    if (D->n_boxes > 0) {
+        std::vector<float4> bx((size_t)4 * D->n_boxes);
+        for (int b = 0; b < D->n_boxes; ++b) {
+            const double *B = D->boxes + 15 * b;
+            for (int a = 0; a < 3; ++a) {
+                const double *u = B + 6 + 3 * a;
+                const double w = -(u[0] * B[0] + u[1] * B[1] + u[2] * B[2]);
+                bx[4 * b + a] = make_float4((float)u[0], (float)u[1], (float)u[2], (float)w);
+            }
+            bx[4 * b + 3] = make_float4((float)B[3], (float)B[4], (float)B[5], 0.f);
+        }
+        if ((rc = dev_upload(&p->d_box, bx.data(), bx.size())) != ST_OK) return rc;
+        sc.box = p->d_box;
+    }
     // sphere centres at q_g for the goal-state tests
     ST_HIP(hipMalloc((void **)&p->d_goal, std::max(S, 1) * sizeof(float4)));
     sc.goal = nullptr;
@@ -260,6 +303,27 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     ST_HIP(hipDeviceSynchronize());
     sc.goal = p->d_goal;
     if (scene_lds_bytes(sc) > 64 * 1024) return fail(ST_EINVAL, "obstacle table too large for LDS");
+    // the static terms at q_g, decided once by the state test itself with the
+    // moving obstacles left out
+    sc.goal_blocked = 0;
+    if (sc.stat) {
+        SceneDev s2 = sc;
+        s2.O = 0;
+        s2.O_pad = 0;
+        float xg[kMaxDof + 1];
+        for (int j = 0; j < d; ++j) xg[j] = sc.q_g[j];
+        xg[d] = 0.f;
+        float *dx = nullptr;
+        uint8_t *dfree = nullptr, hfree = 0;
+        ST_HIP(hipMalloc((void **)&dx, sizeof xg));
+        ST_HIP(hipMalloc((void **)&dfree, 1));
+        ST_HIP(hipMemcpy(dx, xg, (d + 1) * sizeof(float), hipMemcpyHostToDevice));
+        ST_HIP(launch_check_states(s2, 1, dx, dfree, 0));
+        ST_HIP(hipMemcpy(&hfree, dfree, 1, hipMemcpyDeviceToHost));
+        ST_HIP(hipFree(dx));
+        ST_HIP(hipFree(dfree));
+        sc.goal_blocked = hfree ? 0 : 1;
+    }
     return ST_OK;
 }
 
@@ -433,7 +497,7 @@ static void destroy(st_problem *p) {
     edge_bufs_free(p->ebufs);
     edge_bufs_free(p->ebufs_api);
     for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
+    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_box, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
                     p->tree.x, p->tree.parent, p->tree.cost, p->tree.rootT, p->d_plan};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

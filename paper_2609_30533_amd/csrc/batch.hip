@@ -147,7 +147,8 @@ static int batch_build(st_batch *b) {
         pls[m] = p->d_plan;
         all.push_back(m);
         (p->prm.variant == ST_INTERVAL_ROOT ? ir : rr).push_back(m);
-        cls[std::make_tuple(p->sc.kind, p->sc.ot, p->sc.obs_mode, a.edge_ext.split_shift, a.edge_br.split_shift)]
+        cls[std::make_tuple(p->sc.stat ? (int)kDHStatic : p->sc.kind, p->sc.ot, p->sc.obs_mode, a.edge_ext.split_shift,
+                            a.edge_br.split_shift)]
             .push_back(m);
         L.mt_nn = std::max(L.mt_nn, a.mt_nn);
         L.mt_br = std::max(L.mt_br, a.mt_br);

@@ -508,8 +508,8 @@ static int ot_for(int O_pad) {
 template <int V>
 using IC = std::integral_constant<int, V>;
 
-// Calls f(IC<KIND>, IC<OT>, IC<OBS>) for the scene's robot kind, obstacle tile
-// and obstacle-time mode.
+// Calls f(IC<KIND>, IC<OT>, IC<OBS>) for the scene's robot kind (an arm with
+// static geometry as kDHStatic), obstacle tile and obstacle-time mode.
 template <class F>
 static void dispatch_scene(const SceneDev &sc, F &&f) {
     auto by_ot = [&](auto kind, auto obs) {
@@ -524,6 +524,7 @@ static void dispatch_scene(const SceneDev &sc, F &&f) {
         else by_ot(kind, IC<kObsGeneric>{});
     };
     if (sc.kind == kTranslate) by_obs(IC<kTranslate>{});
+    else if (sc.stat) by_obs(IC<kDHStatic>{});
     else by_obs(IC<kDH>{});
 }
 

@@ -25,7 +25,9 @@ namespace st {
 constexpr int kMaxDof = 7;
 constexpr int kWave = 64;
 
-enum { kTranslate = 0, kDH = 1 };
+// Robot kinds as kernel template arguments: kDHStatic is an arm whose state
+// test also covers its listed link pairs and the fixed boxes.
+enum { kTranslate = 0, kDH = 1, kDHStatic = 2 };
 enum { kObsShared = 0, kObsGeneric = 1 };
 
 // Every robot/obstacle pair is tested against (r_s + r_o + kClearanceEps)^2:
@@ -43,6 +45,12 @@ struct SceneDev {
     float dh_a[8], dh_ca[8], dh_sa[8], dh_d[8], dh_t0[8];
     int link_first[9];          // spheres of link l are [link_first[l], link_first[l+1])
     int lds_goal;               // float4 offset in LDS of the sphere centres at q_g
+    // static geometry (arms): self_mask[lb] bit la = link pair (la, lb) tested;
+    // boxes as 4 float4 rows: (axis_a, -axis_a . centre) for a = 0..2, then
+    // (half extents, 0).  goal_blocked: q_g fails the static terms.
+    int stat, n_box, lds_box, goal_blocked;
+    unsigned self_mask[kMaxDof + 1];
+    const float4 *box;          // [n_box][4]
     const float4 *sph;          // [S]
     const float4 *goal;         // [S] world centres at q_g (x, y, z, |c|^2)
     const float *obs_r;         // [O] obstacle radii (the continuous check)
@@ -66,6 +74,7 @@ __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds)
     }
     if (sc.goal)
         for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_goal + i] = sc.goal[i];
+    for (int i = threadIdx.x; i < 4 * sc.n_box; i += blockDim.x) lds[sc.lds_box + i] = sc.box[i];
     __syncthreads();
 }
 
@@ -97,6 +106,24 @@ __device__ __forceinline__ void dh_compose(const SceneDev &sc, int j, float qj, 
     u = fmaf(f.R20, ct, f.R21 * st_); w = fmaf(f.R21, ct, -f.R20 * st_);
     f.p2 = fmaf(a, u, fmaf(dd, f.R22, f.p2));
     f.R20 = u; f.R21 = fmaf(ca, w, sa * f.R22); f.R22 = fmaf(ca, f.R22, -sa * w);
+}
+
+// Frame of link b expressed in the frame of link a: R = Ra^T Rb,
+// p = Ra^T (pb - pa).
+__device__ __forceinline__ void frame_relative(const Frame &a, const Frame &b, Frame &m) {
+    m.R00 = fmaf(a.R00, b.R00, fmaf(a.R10, b.R10, a.R20 * b.R20));
+    m.R01 = fmaf(a.R00, b.R01, fmaf(a.R10, b.R11, a.R20 * b.R21));
+    m.R02 = fmaf(a.R00, b.R02, fmaf(a.R10, b.R12, a.R20 * b.R22));
+    m.R10 = fmaf(a.R01, b.R00, fmaf(a.R11, b.R10, a.R21 * b.R20));
+    m.R11 = fmaf(a.R01, b.R01, fmaf(a.R11, b.R11, a.R21 * b.R21));
+    m.R12 = fmaf(a.R01, b.R02, fmaf(a.R11, b.R12, a.R21 * b.R22));
+    m.R20 = fmaf(a.R02, b.R00, fmaf(a.R12, b.R10, a.R22 * b.R20));
+    m.R21 = fmaf(a.R02, b.R01, fmaf(a.R12, b.R11, a.R22 * b.R21));
+    m.R22 = fmaf(a.R02, b.R02, fmaf(a.R12, b.R12, a.R22 * b.R22));
+    const float dx = b.p0 - a.p0, dy = b.p1 - a.p1, dz = b.p2 - a.p2;
+    m.p0 = fmaf(a.R00, dx, fmaf(a.R10, dy, a.R20 * dz));
+    m.p1 = fmaf(a.R01, dx, fmaf(a.R11, dy, a.R21 * dz));
+    m.p2 = fmaf(a.R02, dx, fmaf(a.R12, dy, a.R22 * dz));
 }
 
 // World centre of a sphere given in its link frame, and |c|^2.
@@ -175,6 +202,51 @@ __device__ __forceinline__ uint64_t pair_hits(const float4 *lds, const SceneDev 
         m |= __ballot(v < r2[i]);
     }
     return m;
+}
+
+// Does a sphere (world centre c, radius r) reach into any fixed box?  Per box
+// the offsets along its axes, their excess over the half extents, and the
+// squared distance to the closed box against (r + eps)^2.
+__device__ __forceinline__ bool box_hits(const float4 *lds, const SceneDev &sc, float cx, float cy, float cz,
+                                         float r) {
+    const float rr = r + (float)kClearanceEps;
+    const float r2 = rr * rr;
+    bool h = false;
+    for (int b = 0; b < sc.n_box; ++b) {
+        const float4 *B = lds + sc.lds_box + 4 * b;
+        const float4 a0 = B[0], a1 = B[1], a2 = B[2], hb = B[3];
+        const float u0 = fmaf(a0.x, cx, fmaf(a0.y, cy, fmaf(a0.z, cz, a0.w)));
+        const float u1 = fmaf(a1.x, cx, fmaf(a1.y, cy, fmaf(a1.z, cz, a1.w)));
+        const float u2 = fmaf(a2.x, cx, fmaf(a2.y, cy, fmaf(a2.z, cz, a2.w)));
+        const float e0 = fmaxf(fabsf(u0) - hb.x, 0.0f);
+        const float e1 = fmaxf(fabsf(u1) - hb.y, 0.0f);
+        const float e2 = fmaxf(fabsf(u2) - hb.z, 0.0f);
+        h = h || fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) < r2;
+    }
+    return h;
+}
+
+// Spheres [s0, s1) of link b, offsets p_b, against spheres [a0, a1) of link a,
+// with m the frame of b in the frame of a: a pair collides iff
+// |m p_b - p_a| < r_a + r_b + eps.  `first` is this lane's first sphere of b
+// and `step` its stride (the lane split of a state).
+__device__ __forceinline__ bool link_pair_hits(const float4 *lds, const SceneDev &sc, const Frame &m, int first,
+                                               int s1, int step, int a0, int a1) {
+    bool h = false;
+    for (int s = first; s < s1; s += step) {
+        const float4 sp = lds[sc.lds_sph + s];
+        const float cx = fmaf(m.R00, sp.x, fmaf(m.R01, sp.y, fmaf(m.R02, sp.z, m.p0)));
+        const float cy = fmaf(m.R10, sp.x, fmaf(m.R11, sp.y, fmaf(m.R12, sp.z, m.p1)));
+        const float cz = fmaf(m.R20, sp.x, fmaf(m.R21, sp.y, fmaf(m.R22, sp.z, m.p2)));
+        const float rb = sp.w + (float)kClearanceEps;
+        for (int a = a0; a < a1; ++a) {
+            const float4 pa = lds[sc.lds_sph + a];
+            const float dx = cx - pa.x, dy = cy - pa.y, dz = cz - pa.z;
+            const float R = pa.w + rb;
+            h = h || fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R;
+        }
+    }
+    return h;
 }
 
 // Hit of the lane's state from the lane's accumulated pair masks.  A lane
@@ -275,13 +347,58 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
             }
         }
     }
+    if (KIND == kDHStatic && __ballot(alive) != 0) {
+        // time-independent terms: every link frame is kept (registers), the
+        // link's spheres are tested against the boxes in the world frame and
+        // against each listed lower link in that link's frame
+        Frame F[kMaxDof + 1];
+        frame_identity(F[0]);
+#pragma unroll
+        for (int l = 0; l <= kMaxDof; ++l) {
+            if (l > sc.d) break;
+            if (l > 0) {
+                F[l] = F[l - 1];
+                if (alive) dh_compose(sc, l - 1, q[l - 1], F[l]);
+            }
+            if (__ballot(alive) == 0) break;
+            const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
+            if (s1 <= s0) continue;
+            const int first = s0 + ((part - s0) & (SPLIT - 1));
+            if (sc.n_box > 0 && alive) {
+                bool h = false;
+                for (int s = first; s < s1; s += SPLIT) {
+                    float cx, cy, cz, as;
+                    const float4 sp = lds[sc.lds_sph + s];
+                    sphere_world(F[l], sp, cx, cy, cz, as);
+                    h = h || box_hits(lds, sc, cx, cy, cz, sp.w);
+                }
+                hm |= __ballot(h);
+            }
+#pragma unroll
+            for (int la = 0; la < kMaxDof; ++la) {
+                if (la >= l) break;
+                const int a0 = sc.link_first[la], a1 = sc.link_first[la + 1];
+                if (!((sc.self_mask[l] >> la) & 1u) || a1 <= a0) continue;
+                if (alive) {
+                    Frame m;
+                    frame_relative(F[la], F[l], m);
+                    hm |= __ballot(link_pair_hits(lds, sc, m, first, s1, SPLIT, a0, a1));
+                }
+            }
+            hit = hit || state_hit<SPLIT>(hm, st_lane);
+            const uint64_t mk = __ballot(hit);
+            if (FIRST) alive = alive && !hit && !(mk & lower_mask);
+            else alive = alive && !(mk & group_mask);
+        }
+    }
     return hit;
 }
 
 // Does (q_g, t) collide?  The same decision as state_hits at q = q_g, with
 // the sphere centres at q_g read from LDS (they are computed once per
 // problem by the same kinematics code), so only the obstacle positions at t
-// and the pair tests remain.  SPLIT lanes share a state as in state_hits;
+// and the pair tests remain; the static terms at q_g are decided once per
+// problem by the state test itself (goal_blocked).  SPLIT lanes share a state as in state_hits;
 // lanes are independent otherwise (`alive` false: nothing to check).
 template <int OT, int OBS, int SPLIT>
 __device__ __forceinline__ bool goal_hits(const SceneDev &sc, const float4 *lds, float t, bool alive, int part) {
@@ -289,7 +406,7 @@ __device__ __forceinline__ bool goal_hits(const SceneDev &sc, const float4 *lds,
     bool hit = false;
     uint64_t hm = 0;
     if (alive) {
-        bool out = !(t >= 0.0f) || !(t <= sc.H);
+        bool out = !(t >= 0.0f) || !(t <= sc.H) || sc.goal_blocked;
 #pragma unroll
         for (int j = 0; j < kMaxDof; ++j)
             if (j < sc.d) out = out || !(sc.q_g[j] >= sc.q_lo[j]) || !(sc.q_g[j] <= sc.q_hi[j]);

@@ -44,7 +44,9 @@ class Desc(C.Structure):
                 ("t_min", C.c_double), ("t_max", C.c_double), ("v_max", C.c_double),
                 ("n_obstacles", C.c_int32), ("max_waypoints", C.c_int32),
                 ("n_waypoints", C.POINTER(C.c_int32)), ("waypoints", C.POINTER(C.c_double)),
-                ("obstacle_radius", C.POINTER(C.c_double)), ("params", Params)]
+                ("obstacle_radius", C.POINTER(C.c_double)), ("params", Params),
+                ("n_self_pairs", C.c_int32), ("self_pairs", C.POINTER(C.c_int32)),
+                ("n_boxes", C.c_int32), ("boxes", C.POINTER(C.c_double))]
 
 
 class Samples(C.Structure):
@@ -214,6 +216,12 @@ def make_desc(prob: scenes.Problem, problem_id: int = 0):
     D.params = Params(p.variant, p.n_groups, p.batch, p.eta, p.h, p.dt, p.p_new, p.p_guided, p.cap_fwd,
                       p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF,
                       1 if getattr(p, "no_recycling", 0) else 0)
+    pairs = np.asarray(getattr(prob, "self_pairs", np.zeros((0, 2))), dtype=np.int32).reshape(-1, 2)
+    boxes = np.asarray(getattr(prob, "boxes", np.zeros((0, 15))), dtype=np.float64).reshape(-1, 15)
+    D.n_self_pairs = len(pairs)
+    D.self_pairs = arr(pairs, np.int32) if len(pairs) else None
+    D.n_boxes = len(boxes)
+    D.boxes = arr(boxes, np.float64) if len(boxes) else None
     return D, keep
 
 

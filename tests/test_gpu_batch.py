@@ -34,6 +34,7 @@ def _members():
         _shrink(scenes.arm6(2), 512, 1 << 15, 1 << 12),
         _shrink(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 128, 1 << 14, 1 << 11),
         _shrink(scenes.arm7rr(2, n_obs=8), 320, 1 << 15, 1 << 11, groups=16),
+        _shrink(scenes.arm6static(7), 256, 1 << 15, 1 << 12),
     ]
     for s in range(3):
         m = scenes.mixed(100 + s)
