@@ -43,11 +43,23 @@ def flops_per_state(prob) -> int:
       forward kinematics  69 per joint (3x4 affine product 63 + 6 for A_i),
       sphere centres      18 per sphere (3x3 product and translation),
       obstacle centres     7 per obstacle (segment offset and 3 fused lerps),
-      sphere pairs         8 per pair (3 differences, 3 squares, 2 sums)."""
+      sphere pairs         8 per pair (3 differences, 3 squares, 2 sums).
+    With static geometry (arms) also
+      link pairs          63 per listed pair (relative frame), 18 per sphere of
+                          the upper link, 8 per sphere pair,
+      boxes               26 per sphere and box (axis offsets 18, excess and
+                          squared distance 8)."""
     S, O, d = prob.n_spheres, prob.n_obs, prob.d
     fk = 69 * d if prob.kind == 1 else 3
     sph = 18 * S if prob.kind == 1 else 3 * S
-    return fk + sph + 7 * O + 8 * S * O
+    w = fk + sph + 7 * O + 8 * S * O
+    links = np.asarray(prob.sphere_link)
+    for la, lb in {tuple(p) for p in np.asarray(getattr(prob, "self_pairs", np.zeros((0, 2)))).tolist()}:
+        na, nb = int((links == la).sum()), int((links == lb).sum())
+        if na and nb:
+            w += 63 + 18 * nb + 8 * na * nb
+    w += 26 * S * len(getattr(prob, "boxes", ()))
+    return int(w)
 
 
 def pick_problem(maker, lib, first_seed=0, need_solvable=False, limit=64):
@@ -294,61 +306,10 @@ def ablation(lib, scenes, args):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--roofline-steps", type=int, default=10)
-    ap.add_argument("--ttfs-batch", type=int, default=512, help="evaluation problems (0: skip the comparison)")
-    ap.add_argument("--ttfs-ms", type=float, default=2000.0, help="budget of each batched evaluation run")
-    ap.add_argument("--ttfs-single-ms", type=float, default=1000.0, help="budget of each single-problem run")
-    ap.add_argument("--queue-problems", type=int, default=128, help="problems of the workload comparison (0: skip)")
-    ap.add_argument("--queue-ms", type=float, default=100.0)
-    ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
-    ap.add_argument("--batch-ms", type=float, default=2000.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-reference", type=int, default=0,
-                    help="only copy this many MiB device to device three times (the reference kernel that "
-                         "scales the memory counters of a profile) and exit")
-    ap.add_argument("--ablation", type=int, default=0,
-                    help="only run the recycling ablation on this many problems per condition and print JSON")
-    ap.add_argument("--ablation-ms", type=float, default=1000.0)
-    ap.add_argument("--edge-sweep", type=int, default=0,
-                    help="only time st_check_edges on this many synthetic edges per launch shape and print JSON")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (problems shard across GPUs "
-              "without exchange; see DESIGN.md)", file=sys.stderr)
-        sys.exit(2)
-
+def single_run(gp, prob, args):
+    """The timed steps of one problem (captured iteration graphs on a side
+    stream) and an event-timed pass over the following iterations."""
     import torch
-    from paper_2609_30533_amd import lib, scenes
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    torch.cuda.init()
-
-    if args.copy_reference > 0:
-        n = args.copy_reference * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_reference_bytes": n * 4, "copies": 3}))
-        return
-
-    if args.ablation > 0:
-        for r in ablation(lib, scenes, args):
-            print(json.dumps(r), flush=True)
-        return
-
-    if args.edge_sweep > 0:
-        for r in edge_sweep(lib, scenes, args.edge_sweep):
-            print(json.dumps(r), flush=True)
-        return
-
-    seed, prob, gp = pick_problem(scenes.arm6, lib)
     W = flops_per_state(prob)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
@@ -375,22 +336,20 @@ def main():
         gp.profile(False)
     elapsed = t1 - t0
     edges = (w1["edges"] - w0["edges"]) + (w1["bridges"] - w0["bridges"])
-    value = edges / elapsed
     states = (p1["edge_states"] - p0["edge_states"]) + (p1["bridge_states"] - p0["bridge_states"])
     ms_edge = stages["edge_check"][0] + stages["bridge_check"][0]
     launches = stages["edge_check"][1] + stages["bridge_check"][1]
-    flops = states * W
-    achieved = flops / (ms_edge * 1e-3) / 1e12 if ms_edge > 0 else 0.0
+    achieved = states * W / (ms_edge * 1e-3) / 1e12 if ms_edge > 0 else 0.0
+    return dict(elapsed=elapsed, edges=edges, value=edges / elapsed, states=states, ms_edge=ms_edge,
+                launches=launches, stages=stages, flops_per_state=W, achieved=achieved)
+
+
+def report(args, seed, prob, gp, m, ttfs, batched, cpu):
+    elapsed, edges, value, states, ms_edge, launches, stages = (m[k] for k in (
+        "elapsed", "edges", "value", "states", "ms_edge", "launches", "stages"))
+    W, achieved = m["flops_per_state"], m["achieved"]
     dominant = max(stages, key=lambda k: stages[k][0])
     inf = gp.info()
-
-    ttfs = ttfs_section(lib, args) if args.ttfs_batch > 0 else {}
-    batched = batched_section(lib, args) if args.batch_problems > 0 else {}
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(prob, args.cpu_seconds)
-
     out = {
         "metric": "space-time edge checks/s; median first-solution ms, learned+batched vs plain",
         "value": value,
@@ -425,6 +384,119 @@ def main():
     out.update(ttfs)
     out.update(batched)
     print(json.dumps(out))
+
+
+def static_section(lib, scenes, args):
+    """Self-collision and fixed boxes (the 6-DOF arm with its listed link
+    pairs, a table and a post): the single-problem step throughput on the
+    same configuration as the headline, and time to first solution of a batch
+    of problems with and without the static terms."""
+    seed, prob, gp = pick_problem(scenes.arm6static, lib)
+    m = single_run(gp, prob, args)
+    gp.close()
+    print(json.dumps({"workload": "arm6 with self-collision (10 link pairs) and 2 fixed boxes, interval root N=8, "
+                                  "B=4096", "problem_seed": seed, "edge_checks_per_s": m["value"],
+                      "ms_per_step": m["elapsed"] * 1e3 / args.steps, "flops_per_state": m["flops_per_state"],
+                      "edge_check_tflops": m["achieved"], "frac": m["achieved"] / PEAK_FP32_TFLOPS,
+                      "stages_ms": {k: round(v[0], 4) for k, v in m["stages"].items()}}), flush=True)
+    # evaluation problems whose start and goal clear the static terms (and the
+    # moving obstacles at t = 0), checked with the library's kernels
+    import torch
+    seeds = []
+    s = 0
+    while len(seeds) < args.static and s < 50 * args.static:
+        p = scenes.with_static(eval_problem(s))
+        g = lib.Problem(p)
+        x = torch.tensor(np.r_[p.q_start, 0.0][None], dtype=torch.float32, device="cuda")
+        if g.check_states(x).cpu().numpy()[0] and g.goal_free().any():
+            seeds.append(s)
+        g.close()
+        s += 1
+    res = {}
+    for st in (0, 1):
+        probs = [scenes.with_static(eval_problem(s)) if st else eval_problem(s) for s in seeds]
+        res[st] = batched_run(lib, probs, args.static_ms)
+    fm = [r["first_ms"] for r in (res[0], res[1])]
+    both = np.isfinite(fm[0]) & np.isfinite(fm[1])
+    print(json.dumps({"workload": "%d arm6 problems (B=256) as one batch, %g ms budget, start and goal clear of "
+                                  "the static terms" % (len(seeds), args.static_ms),
+                      "solved_plain": int(res[0]["n_solved"]), "solved_static": int(res[1]["n_solved"]),
+                      "median_first_ms_plain": float(np.median(fm[0][both])) if both.any() else None,
+                      "median_first_ms_static": float(np.median(fm[1][both])) if both.any() else None,
+                      "common": int(both.sum()),
+                      "edges_per_s_plain": res[0]["edges"] / max(res[0]["total_ms"], 1e-9) * 1e3,
+                      "edges_per_s_static": res[1]["edges"] / max(res[1]["total_ms"], 1e-9) * 1e3}), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--roofline-steps", type=int, default=10)
+    ap.add_argument("--ttfs-batch", type=int, default=512, help="evaluation problems (0: skip the comparison)")
+    ap.add_argument("--ttfs-ms", type=float, default=2000.0, help="budget of each batched evaluation run")
+    ap.add_argument("--ttfs-single-ms", type=float, default=1000.0, help="budget of each single-problem run")
+    ap.add_argument("--queue-problems", type=int, default=128, help="problems of the workload comparison (0: skip)")
+    ap.add_argument("--queue-ms", type=float, default=100.0)
+    ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
+    ap.add_argument("--batch-ms", type=float, default=2000.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-reference", type=int, default=0,
+                    help="only copy this many MiB device to device three times (the reference kernel that "
+                         "scales the memory counters of a profile) and exit")
+    ap.add_argument("--ablation", type=int, default=0,
+                    help="only run the recycling ablation on this many problems per condition and print JSON")
+    ap.add_argument("--ablation-ms", type=float, default=1000.0)
+    ap.add_argument("--edge-sweep", type=int, default=0,
+                    help="only time st_check_edges on this many synthetic edges per launch shape and print JSON")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--static", type=int, default=0,
+                    help="self-collision and boxes: throughput and a batch of this many problems (0: skip)")
+    ap.add_argument("--static-ms", type=float, default=1000.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (problems shard across GPUs "
+              "without exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2609_30533_amd import lib, scenes
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    torch.cuda.init()
+
+    if args.copy_reference > 0:
+        n = args.copy_reference * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference_bytes": n * 4, "copies": 3}))
+        return
+
+    if args.ablation > 0:
+        for r in ablation(lib, scenes, args):
+            print(json.dumps(r), flush=True)
+        return
+
+    if args.edge_sweep > 0:
+        for r in edge_sweep(lib, scenes, args.edge_sweep):
+            print(json.dumps(r), flush=True)
+        return
+
+    if args.static > 0:
+        static_section(lib, scenes, args)
+        return
+
+    seed, prob, gp = pick_problem(scenes.arm6, lib)
+    m = single_run(gp, prob, args)
+    ttfs = ttfs_section(lib, args) if args.ttfs_batch > 0 else {}
+    batched = batched_section(lib, args) if args.batch_problems > 0 else {}
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(prob, args.cpu_seconds)
+    report(args, seed, prob, gp, m, ttfs, batched, cpu)
 
 
 if __name__ == "__main__":

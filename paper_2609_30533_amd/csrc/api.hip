@@ -266,6 +266,29 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.n_box = D->n_boxes;
     for (int k = 0; k < D->n_self_pairs; ++k) sc.self_mask[D->self_pairs[2 * k + 1]] |= 1u << D->self_pairs[2 * k];
     sc.stat = (D->n_self_pairs > 0 || D->n_boxes > 0) ? 1 : 0;
+    // per-link bounding spheres of the broad phase: centroid of the link's
+    // sphere centres, radius the farthest sphere surface, rounded outwards
+    for (int l = 0; l <= d && l <= kMaxDof; ++l) {
+        double c[3] = {0, 0, 0};
+        int n = 0;
+        for (int i = 0; i < S; ++i)
+            if (D->sphere_link[ord[i]] == l) {
+                for (int k = 0; k < 3; ++k) c[k] += D->spheres[4 * ord[i] + k];
+                ++n;
+            }
+        if (n == 0) continue;
+        for (int k = 0; k < 3; ++k) c[k] /= n;
+        const float cf[3] = {(float)c[0], (float)c[1], (float)c[2]};
+        double rho = 0;
+        for (int i = 0; i < S; ++i)
+            if (D->sphere_link[ord[i]] == l) {
+                const double *sp = D->spheres + 4 * ord[i];
+                const double e = sqrt((sp[0] - cf[0]) * (sp[0] - cf[0]) + (sp[1] - cf[1]) * (sp[1] - cf[1]) +
+                                      (sp[2] - cf[2]) * (sp[2] - cf[2]));
+                rho = std::max(rho, e + sp[3]);
+            }
+        sc.lbs[l] = make_float4(cf[0], cf[1], cf[2], (float)(rho * (1.0 + 1e-6) + 1e-6));
+    }
     int rc;
     if ((rc = dev_upload(&p->d_sph, sph.data(), sph.size())) != ST_OK) return rc;
     if ((rc = dev_upload(&p->d_R2, R2.data(), R2.size())) != ST_OK) return rc;

@@ -50,6 +50,7 @@ struct SceneDev {
     // (half extents, 0).  goal_blocked: q_g fails the static terms.
     int stat, n_box, lds_box, goal_blocked;
     unsigned self_mask[kMaxDof + 1];
+    float4 lbs[kMaxDof + 1];    // per link: bounding sphere of its spheres (link frame centre, radius)
     const float4 *box;          // [n_box][4]
     const float4 *sph;          // [S]
     const float4 *goal;         // [S] world centres at q_g (x, y, z, |c|^2)
@@ -204,26 +205,19 @@ __device__ __forceinline__ uint64_t pair_hits(const float4 *lds, const SceneDev 
     return m;
 }
 
-// Does a sphere (world centre c, radius r) reach into any fixed box?  Per box
-// the offsets along its axes, their excess over the half extents, and the
-// squared distance to the closed box against (r + eps)^2.
-__device__ __forceinline__ bool box_hits(const float4 *lds, const SceneDev &sc, float cx, float cy, float cz,
-                                         float r) {
-    const float rr = r + (float)kClearanceEps;
-    const float r2 = rr * rr;
-    bool h = false;
-    for (int b = 0; b < sc.n_box; ++b) {
-        const float4 *B = lds + sc.lds_box + 4 * b;
-        const float4 a0 = B[0], a1 = B[1], a2 = B[2], hb = B[3];
-        const float u0 = fmaf(a0.x, cx, fmaf(a0.y, cy, fmaf(a0.z, cz, a0.w)));
-        const float u1 = fmaf(a1.x, cx, fmaf(a1.y, cy, fmaf(a1.z, cz, a1.w)));
-        const float u2 = fmaf(a2.x, cx, fmaf(a2.y, cy, fmaf(a2.z, cz, a2.w)));
-        const float e0 = fmaxf(fabsf(u0) - hb.x, 0.0f);
-        const float e1 = fmaxf(fabsf(u1) - hb.y, 0.0f);
-        const float e2 = fmaxf(fabsf(u2) - hb.z, 0.0f);
-        h = h || fmaf(e0, e0, fmaf(e1, e1, e2 * e2)) < r2;
-    }
-    return h;
+// Squared distance from point c to fixed box b: offsets along the box axes,
+// their excess over the half extents (zero inside), and the squared norm.
+__device__ __forceinline__ float box_dist2(const float4 *lds, const SceneDev &sc, int b, float cx, float cy,
+                                           float cz) {
+    const float4 *B = lds + sc.lds_box + 4 * b;
+    const float4 a0 = B[0], a1 = B[1], a2 = B[2], hb = B[3];
+    const float u0 = fmaf(a0.x, cx, fmaf(a0.y, cy, fmaf(a0.z, cz, a0.w)));
+    const float u1 = fmaf(a1.x, cx, fmaf(a1.y, cy, fmaf(a1.z, cz, a1.w)));
+    const float u2 = fmaf(a2.x, cx, fmaf(a2.y, cy, fmaf(a2.z, cz, a2.w)));
+    const float e0 = fmaxf(fabsf(u0) - hb.x, 0.0f);
+    const float e1 = fmaxf(fabsf(u1) - hb.y, 0.0f);
+    const float e2 = fmaxf(fabsf(u2) - hb.z, 0.0f);
+    return fmaf(e0, e0, fmaf(e1, e1, e2 * e2));
 }
 
 // Spheres [s0, s1) of link b, offsets p_b, against spheres [a0, a1) of link a,
@@ -247,6 +241,83 @@ __device__ __forceinline__ bool link_pair_hits(const float4 *lds, const SceneDev
         }
     }
     return h;
+}
+
+// Broad phase of the static terms: a link's spheres lie inside its bounding
+// sphere (centre and radius per link, in the link frame); when two bounding
+// spheres, or a bounding sphere and a box, are more than kBroadMargin apart,
+// every sphere pair between them clears contact by that much and the exact
+// tests are skipped (they could only report free).
+constexpr float kBroadMargin = 1e-3f;
+
+template <int SPLIT>
+__device__ __forceinline__ bool state_hit(uint64_t hm, int st_lane);
+
+// Self-collision of the listed link pairs and the fixed boxes for the lane's
+// configuration q (time-independent).  Every link frame is kept in
+// registers; per link, the spheres near a box are tested against it in the
+// world frame and, per listed lower link whose bound is near, against that
+// link's spheres in its frame (one relative transform per link pair).
+// Updates hit / hm / alive as the obstacle tiles do.  Every lane of the wave
+// must call this.
+template <bool FIRST, int SPLIT>
+__device__ __forceinline__ void static_pass(const SceneDev &sc, const float4 *lds, const float *q, bool &alive,
+                                            bool &hit, uint64_t &hm, uint64_t group_mask, uint64_t lower_mask,
+                                            int part, int st_lane) {
+    Frame F[kMaxDof + 1];
+    frame_identity(F[0]);
+#pragma unroll
+    for (int l = 0; l <= kMaxDof; ++l) {
+        if (l > sc.d) break;
+        if (l > 0) {
+            F[l] = F[l - 1];
+            if (alive) dh_compose(sc, l - 1, q[l - 1], F[l]);
+        }
+        if (__ballot(alive) == 0) break;
+        const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
+        if (s1 <= s0) continue;
+        const int first = s0 + ((part - s0) & (SPLIT - 1));
+        const float4 bl = sc.lbs[l];
+        bool h = false;
+        if (sc.n_box > 0 && alive) {
+            float bx, by, bz, bs;
+            sphere_world(F[l], bl, bx, by, bz, bs);
+            const float rb = bl.w + kBroadMargin;
+            for (int b = 0; b < sc.n_box; ++b) {
+                if (box_dist2(lds, sc, b, bx, by, bz) < rb * rb) {
+                    for (int s = first; s < s1; s += SPLIT) {
+                        float cx, cy, cz, as;
+                        const float4 sp = lds[sc.lds_sph + s];
+                        sphere_world(F[l], sp, cx, cy, cz, as);
+                        const float rr = sp.w + (float)kClearanceEps;
+                        h = h || box_dist2(lds, sc, b, cx, cy, cz) < rr * rr;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int la = 0; la < kMaxDof; ++la) {
+            if (la >= l) break;
+            const int a0 = sc.link_first[la], a1 = sc.link_first[la + 1];
+            if (!((sc.self_mask[l] >> la) & 1u) || a1 <= a0) continue;
+            if (alive) {
+                Frame m;
+                frame_relative(F[la], F[l], m);
+                const float4 ba = sc.lbs[la];
+                const float dx = fmaf(m.R00, bl.x, fmaf(m.R01, bl.y, fmaf(m.R02, bl.z, m.p0))) - ba.x;
+                const float dy = fmaf(m.R10, bl.x, fmaf(m.R11, bl.y, fmaf(m.R12, bl.z, m.p1))) - ba.y;
+                const float dz = fmaf(m.R20, bl.x, fmaf(m.R21, bl.y, fmaf(m.R22, bl.z, m.p2))) - ba.z;
+                const float R = ba.w + bl.w + kBroadMargin;
+                if (fmaf(dx, dx, fmaf(dy, dy, dz * dz)) < R * R)
+                    h = h || link_pair_hits(lds, sc, m, first, s1, SPLIT, a0, a1);
+            }
+        }
+        hm |= __ballot(h);
+        hit = hit || state_hit<SPLIT>(hm, st_lane);
+        const uint64_t mk = __ballot(hit);
+        if (FIRST) alive = alive && !hit && !(mk & lower_mask);
+        else alive = alive && !(mk & group_mask);
+    }
 }
 
 // Hit of the lane's state from the lane's accumulated pair masks.  A lane
@@ -347,50 +418,9 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
             }
         }
     }
-    if (KIND == kDHStatic && __ballot(alive) != 0) {
-        // time-independent terms: every link frame is kept (registers), the
-        // link's spheres are tested against the boxes in the world frame and
-        // against each listed lower link in that link's frame
-        Frame F[kMaxDof + 1];
-        frame_identity(F[0]);
-#pragma unroll
-        for (int l = 0; l <= kMaxDof; ++l) {
-            if (l > sc.d) break;
-            if (l > 0) {
-                F[l] = F[l - 1];
-                if (alive) dh_compose(sc, l - 1, q[l - 1], F[l]);
-            }
-            if (__ballot(alive) == 0) break;
-            const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
-            if (s1 <= s0) continue;
-            const int first = s0 + ((part - s0) & (SPLIT - 1));
-            if (sc.n_box > 0 && alive) {
-                bool h = false;
-                for (int s = first; s < s1; s += SPLIT) {
-                    float cx, cy, cz, as;
-                    const float4 sp = lds[sc.lds_sph + s];
-                    sphere_world(F[l], sp, cx, cy, cz, as);
-                    h = h || box_hits(lds, sc, cx, cy, cz, sp.w);
-                }
-                hm |= __ballot(h);
-            }
-#pragma unroll
-            for (int la = 0; la < kMaxDof; ++la) {
-                if (la >= l) break;
-                const int a0 = sc.link_first[la], a1 = sc.link_first[la + 1];
-                if (!((sc.self_mask[l] >> la) & 1u) || a1 <= a0) continue;
-                if (alive) {
-                    Frame m;
-                    frame_relative(F[la], F[l], m);
-                    hm |= __ballot(link_pair_hits(lds, sc, m, first, s1, SPLIT, a0, a1));
-                }
-            }
-            hit = hit || state_hit<SPLIT>(hm, st_lane);
-            const uint64_t mk = __ballot(hit);
-            if (FIRST) alive = alive && !hit && !(mk & lower_mask);
-            else alive = alive && !(mk & group_mask);
-        }
-    }
+    // time-independent terms for the lanes still undecided
+    if (KIND == kDHStatic && __ballot(alive) != 0)
+        static_pass<FIRST, SPLIT>(sc, lds, q, alive, hit, hm, group_mask, lower_mask, part, st_lane);
     return hit;
 }
 
