@@ -261,7 +261,8 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.lds_t = sc.lds_r2 + (S * sc.O_pad + 3) / 4;
     sc.lds_goal = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));
     sc.lds_box = sc.lds_goal + S;
-    sc.lds_f4 = sc.lds_box + 4 * D->n_boxes;
+    sc.lds_lbr = sc.lds_box + 4 * D->n_boxes;
+    sc.lds_f4 = sc.lds_lbr + (sc.kind == kDH ? ((d + 1) * sc.O_pad + 3) / 4 : 0);
     // static geometry: link-pair masks and boxes as (axis, -axis . centre) rows
     sc.n_box = D->n_boxes;
     for (int k = 0; k < D->n_self_pairs; ++k) sc.self_mask[D->self_pairs[2 * k + 1]] |= 1u << D->self_pairs[2 * k];
@@ -288,6 +289,20 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
                 rho = std::max(rho, e + sp[3]);
             }
         sc.lbs[l] = make_float4(cf[0], cf[1], cf[2], (float)(rho * (1.0 + 1e-6) + 1e-6));
+    }
+    // broad-phase thresholds of links against the moving obstacles
+    if (sc.kind == kDH) {
+        std::vector<float> thr((size_t)(d + 1) * sc.O_pad, -1.0f);
+        for (int l = 0; l <= d; ++l) {
+            if (sc.link_first[l + 1] <= sc.link_first[l]) continue;
+            for (int o = 0; o < O; ++o) {
+                const double R = (double)sc.lbs[l].w + D->obstacle_radius[o] + (double)kBroadMargin;
+                thr[(size_t)l * sc.O_pad + o] = (float)(R * R);
+            }
+        }
+        const int rcl = dev_upload(&p->d_lbr, thr.data(), thr.size());
+        if (rcl != ST_OK) return rcl;
+        sc.lbr = p->d_lbr;
     }
     int rc;
     if ((rc = dev_upload(&p->d_sph, sph.data(), sph.size())) != ST_OK) return rc;
@@ -520,7 +535,7 @@ static void destroy(st_problem *p) {
     edge_bufs_free(p->ebufs);
     edge_bufs_free(p->ebufs_api);
     for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_box, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
+    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_box, p->d_lbr, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
                     p->tree.x, p->tree.parent, p->tree.cost, p->tree.rootT, p->d_plan};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

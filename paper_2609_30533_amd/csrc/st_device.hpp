@@ -51,6 +51,8 @@ struct SceneDev {
     int stat, n_box, lds_box, goal_blocked;
     unsigned self_mask[kMaxDof + 1];
     float4 lbs[kMaxDof + 1];    // per link: bounding sphere of its spheres (link frame centre, radius)
+    int lds_lbr;                // float4 offset in LDS of the [d+1][O_pad] broad-phase thresholds
+    const float *lbr;           // (rho_l + r_o + kBroadMargin)^2, -1 for links without spheres
     const float4 *box;          // [n_box][4]
     const float4 *sph;          // [S]
     const float4 *goal;         // [S] world centres at q_g (x, y, z, |c|^2)
@@ -76,6 +78,10 @@ __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds)
     if (sc.goal)
         for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_goal + i] = sc.goal[i];
     for (int i = threadIdx.x; i < 4 * sc.n_box; i += blockDim.x) lds[sc.lds_box + i] = sc.box[i];
+    if (sc.lbr) {
+        float *lt = reinterpret_cast<float *>(lds + sc.lds_lbr);
+        for (int i = threadIdx.x; i < (sc.d + 1) * sc.O_pad; i += blockDim.x) lt[i] = sc.lbr[i];
+    }
     __syncthreads();
 }
 
@@ -320,6 +326,71 @@ __device__ __forceinline__ void static_pass(const SceneDev &sc, const float4 *ld
     }
 }
 
+// pair_hits restricted to the obstacles of the tile whose bit is set in the
+// wave-uniform mask `near` (the others are known to be clear of the link).
+template <int OT>
+__device__ __forceinline__ uint64_t pair_hits_near(const float4 *lds, const SceneDev &sc, int s, int tile, float cx,
+                                                   float cy, float cz, float as, const float *nx, const float *ny,
+                                                   const float *nz, const float *bo, uint32_t near) {
+    const float4 *r4 = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(lds + sc.lds_r2) +
+                                                        s * sc.O_pad + tile);
+    float r2[OT];
+#pragma unroll
+    for (int i = 0; i < OT / 4; ++i) {
+        const float4 v = r4[i];
+        r2[4 * i] = v.x;
+        r2[4 * i + 1] = v.y;
+        r2[4 * i + 2] = v.z;
+        r2[4 * i + 3] = v.w;
+    }
+    uint64_t m = 0;
+#pragma unroll
+    for (int i = 0; i < OT; ++i) {
+        if ((near >> i) & 1u) {
+            float v = as + bo[i];
+            v = fmaf(cx, nx[i], v);
+            v = fmaf(cy, ny[i], v);
+            v = fmaf(cz, nz[i], v);
+            m |= __ballot(v < r2[i]);
+        }
+    }
+    return m;
+}
+
+// Broad phase of a link against the OT obstacles of a tile: the obstacles
+// that come within rho_l + r_o + kBroadMargin of the link's bounding sphere
+// for some live lane of the wave (wave-uniform bit mask).  A clear obstacle
+// is at least kBroadMargin from every sphere of the link, where the exact
+// test could only report free.
+template <int OT>
+__device__ __forceinline__ uint32_t link_near(const float4 *lds, const SceneDev &sc, int l, int tile, const Frame &f,
+                                              bool alive, const float *nx, const float *ny, const float *nz,
+                                              const float *bo) {
+    float bx, by, bz, bs;
+    sphere_world(f, sc.lbs[l], bx, by, bz, bs);
+    const float4 *t4 = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(lds + sc.lds_lbr) +
+                                                        l * sc.O_pad + tile);
+    float thr[OT];
+#pragma unroll
+    for (int i = 0; i < OT / 4; ++i) {
+        const float4 v = t4[i];
+        thr[4 * i] = v.x;
+        thr[4 * i + 1] = v.y;
+        thr[4 * i + 2] = v.z;
+        thr[4 * i + 3] = v.w;
+    }
+    uint32_t near = 0;
+#pragma unroll
+    for (int i = 0; i < OT; ++i) {
+        float v = bs + bo[i];
+        v = fmaf(bx, nx[i], v);
+        v = fmaf(by, ny[i], v);
+        v = fmaf(bz, nz[i], v);
+        if (__ballot(alive && v < thr[i]) != 0) near |= 1u << i;
+    }
+    return near;
+}
+
 // Hit of the lane's state from the lane's accumulated pair masks.  A lane
 // knows its own bit exactly (its own ballots included it); with SPLIT > 1
 // the lanes of a state ran different numbers of sphere iterations, so their
@@ -333,7 +404,9 @@ __device__ __forceinline__ bool state_hit(uint64_t hm, int st_lane) {
 }
 
 // Does the lane's state (q, t) collide?  OT obstacles are held in registers
-// per tile.  With SPLIT > 1 a state occupies SPLIT adjacent lanes (aligned)
+// per tile; with BROAD the obstacles a link's bounding sphere clears for every
+// live lane of the wave are skipped for that link (exact, see link_near).
+// With SPLIT > 1 a state occupies SPLIT adjacent lanes (aligned)
 // and lane `part` of them tests the spheres s with s = part (mod SPLIT);
 // every lane composes the kinematic chain itself, and a state's hit is the OR
 // over its lanes, so all SPLIT lanes return the same answer.  This divides
@@ -346,7 +419,7 @@ __device__ __forceinline__ bool state_hit(uint64_t hm, int st_lane) {
 //           lower_mask holds the lanes of the lower states;
 //   !FIRST: stop as soon as any lane of its group has hit.
 // Every lane of the wave must call this (it contains ballots).
-template <int KIND, int OT, int OBS, bool FIRST, int SPLIT = 1>
+template <int KIND, int OT, int OBS, bool FIRST, int SPLIT = 1, bool BROAD = false>
 __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds, const float *q, float t, bool alive,
                                            uint64_t group_mask, uint64_t lower_mask, int part = 0) {
     static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4 || SPLIT == 8, "state split");
@@ -403,11 +476,23 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
                 const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
                 if (s1 > s0 && __ballot(alive) != 0) {
                     // this lane's spheres of the link: s = part (mod SPLIT)
-                    for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
-                        if (alive) {
-                            float cx, cy, cz, as;
-                            sphere_world(f, lds[sc.lds_sph + s], cx, cy, cz, as);
-                            hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
+                    if (BROAD) {
+                        const uint32_t near = link_near<OT>(lds, sc, l, tile, f, alive, nx, ny, nz, bo);
+                        if (near != 0)
+                            for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
+                                if (alive) {
+                                    float cx, cy, cz, as;
+                                    sphere_world(f, lds[sc.lds_sph + s], cx, cy, cz, as);
+                                    hm |= pair_hits_near<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo, near);
+                                }
+                            }
+                    } else {
+                        for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
+                            if (alive) {
+                                float cx, cy, cz, as;
+                                sphere_world(f, lds[sc.lds_sph + s], cx, cy, cz, as);
+                                hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
+                            }
                         }
                     }
                     hit = hit || state_hit<SPLIT>(hm, st_lane);

@@ -160,6 +160,7 @@ struct st_problem {
     float4 *d_goal = nullptr;  // sphere centres at q_g
     float *d_obs_r = nullptr;  // obstacle radii
     float4 *d_box = nullptr;   // static boxes, 4 rows each
+    float *d_lbr = nullptr;    // broad-phase thresholds [d+1][O_pad]
     float *d_segt = nullptr;
     // goal grid and windows
     int64_t k_lo = 0, k_hi = -1;
