@@ -179,14 +179,16 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     std::iota(ord.begin(), ord.end(), 0);
     std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return D->sphere_link[a] < D->sphere_link[b]; });
     std::vector<float4> sph(S);
-    std::vector<float> R2((size_t)S * sc.O_pad, -1.0f);
     for (int i = 0; i < S; ++i) {
         const double *s = D->spheres + 4 * ord[i];
         sph[i] = make_float4((float)s[0], (float)s[1], (float)s[2], (float)s[3]);
-        for (int o = 0; o < O; ++o) {
-            const double R = s[3] + D->obstacle_radius[o] + kClearanceEps;
-            R2[(size_t)i * sc.O_pad + o] = (float)(R * R);
-        }
+    }
+    // obstacle radii padded with zeros; the common radius when all agree
+    std::vector<float> ro((size_t)sc.O_pad, 0.0f);
+    sc.r_uni = O > 0 ? (float)D->obstacle_radius[0] : -1.0f;
+    for (int o = 0; o < O; ++o) {
+        ro[o] = (float)D->obstacle_radius[o];
+        if (ro[o] != sc.r_uni) sc.r_uni = -1.0f;
     }
     for (int l = 0; l <= 8; ++l) {
         int c = 0;
@@ -257,12 +259,10 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     if (shared && O == 0) segt.assign(nseg + 1, INFINITY);
     // LDS: segment table, spheres, pair table (padded to float4), times
     sc.lds_sph = sc.O_pad * nseg * 2;
-    sc.lds_r2 = sc.lds_sph + S;
-    sc.lds_t = sc.lds_r2 + (S * sc.O_pad + 3) / 4;
+    sc.lds_t = sc.lds_sph + S;
     sc.lds_goal = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));
     sc.lds_box = sc.lds_goal + S;
-    sc.lds_lbr = sc.lds_box + 4 * D->n_boxes;
-    sc.lds_f4 = sc.lds_lbr + (sc.kind == kDH ? ((d + 1) * sc.O_pad + 3) / 4 : 0);
+    sc.lds_f4 = sc.lds_box + 4 * D->n_boxes;
     // static geometry: link-pair masks and boxes as (axis, -axis . centre) rows
     sc.n_box = D->n_boxes;
     for (int k = 0; k < D->n_self_pairs; ++k) sc.self_mask[D->self_pairs[2 * k + 1]] |= 1u << D->self_pairs[2 * k];
@@ -290,27 +290,13 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
             }
         sc.lbs[l] = make_float4(cf[0], cf[1], cf[2], (float)(rho * (1.0 + 1e-6) + 1e-6));
     }
-    // broad-phase thresholds of links against the moving obstacles
-    if (sc.kind == kDH) {
-        std::vector<float> thr((size_t)(d + 1) * sc.O_pad, -1.0f);
-        for (int l = 0; l <= d; ++l) {
-            if (sc.link_first[l + 1] <= sc.link_first[l]) continue;
-            for (int o = 0; o < O; ++o) {
-                const double R = (double)sc.lbs[l].w + D->obstacle_radius[o] + (double)kBroadMargin;
-                thr[(size_t)l * sc.O_pad + o] = (float)(R * R);
-            }
-        }
-        const int rcl = dev_upload(&p->d_lbr, thr.data(), thr.size());
-        if (rcl != ST_OK) return rcl;
-        sc.lbr = p->d_lbr;
-    }
     int rc;
     if ((rc = dev_upload(&p->d_sph, sph.data(), sph.size())) != ST_OK) return rc;
-    if ((rc = dev_upload(&p->d_R2, R2.data(), R2.size())) != ST_OK) return rc;
+    if ((rc = dev_upload(&p->d_ro, ro.data(), ro.size())) != ST_OK) return rc;
     if ((rc = dev_upload(&p->d_seg, seg.data(), seg.size())) != ST_OK) return rc;
     if ((rc = dev_upload(&p->d_segt, segt.data(), segt.size())) != ST_OK) return rc;
     sc.sph = p->d_sph;
-    sc.R2 = p->d_R2;
+    sc.ro = p->d_ro;
     sc.seg = p->d_seg;
     sc.seg_t = p->d_segt;
     // obstacle radii for the continuous check
@@ -535,7 +521,7 @@ static void destroy(st_problem *p) {
     edge_bufs_free(p->ebufs);
     edge_bufs_free(p->ebufs_api);
     for (hipEvent_t ev : p->prof_ev) (void)hipEventDestroy(ev);
-    void *bufs[] = {p->d_sph, p->d_R2, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_box, p->d_lbr, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
+    void *bufs[] = {p->d_sph, p->d_ro, p->d_seg, p->d_segt, p->d_goal, p->d_obs_r, p->d_box, p->d_gfree, p->d_wlo, p->d_whi, p->d_wcum,
                     p->tree.x, p->tree.parent, p->tree.cost, p->tree.rootT, p->d_plan};
     for (void *b : bufs)
         if (b) (void)hipFree(b);

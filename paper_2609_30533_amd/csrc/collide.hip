@@ -420,7 +420,7 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
 #pragma unroll
             for (int k = 0; k < kMaxDof; ++k) q[k] = 0.f;
         }
-        const bool hit = state_hits<KIND, OT, OBS, true, 1, true>(sc, lds, q, t, act, seg, lower);
+        const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, q, t, act, seg, lower);
         if (hit && act) atomicMin(&s_hit[i], j);
         __syncthreads();
     }

@@ -1,23 +1,23 @@
 // st_device.hpp -- device-side data layout and collision primitives (gfx950).
 //
 // Layout in HBM (all owned by the problem handle):
-//   scene:  spheres sorted by link [S] float4 (x, y, z, r); the pair table
-//           R2[s][o] = (r_s + r_o + eps)^2 (-1 for padding obstacles); the obstacle
-//           segment table [O_pad][n_seg][2] float4 pre-scaled by -2:
-//           (-2 p_k, t_k) and (-2 v_k, span_k); waypoint times [O_pad][n_seg+1].
+//   scene:  spheres sorted by link [S] float4 (x, y, z, r); obstacle radii
+//           [O_pad] (0 for padding obstacles); the obstacle segment table
+//           [O_pad][n_seg][2] float4 pre-scaled by -2: (-2 p_k, t_k) and
+//           (-2 v_k, span_k); waypoint times [O_pad][n_seg+1].
 //   trees:  SoA x[d+1][total] (configuration rows, then time), parent[total],
 //           cost[total], rootT[total]; pool p occupies [base(p), base(p)+cap(p)).
 //
 // The collision test keeps one space-time state per lane.  Forward kinematics
 // runs in registers with the DH constants from the kernel arguments; sphere
-// offsets and the pair table are staged in LDS and read as broadcasts;
-// obstacle centres at the lane's own time come from the segment table, also
-// staged in LDS.  A pair collides iff
-//   |c|^2 + |o|^2 - 2 c.o < (r_s + r_o)^2,
-// evaluated as a_s + b_o + c.n with n = -2 o (four FMA-class ops and a compare).
+// offsets are staged in LDS and read as broadcasts; obstacle centres at the
+// lane's own time come from the segment table, also staged in LDS.  A pair
+// collides iff |c - o| < r_s + r_o + eps, evaluated in expanded form as a
+// minimum over the obstacle tile (sphere_clear).
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <type_traits>
 #include <stdint.h>
 
 namespace st {
@@ -37,7 +37,7 @@ constexpr double kClearanceEps = 2e-5;
 
 struct SceneDev {
     int d, kind, S, O, O_pad, n_seg, obs_mode, lds_f4;  // lds_f4: float4 slots staged in LDS
-    int lds_sph, lds_r2, lds_t;  // float4 offsets in LDS of the spheres, the pair table, the times
+    int lds_sph, lds_t;         // float4 offsets in LDS of the spheres and the waypoint times
     int ot;                      // obstacles per register tile (4, 8 or 16; divides O_pad)
     float v, H, h, inv_h;
     double v_d, h_d;
@@ -51,13 +51,12 @@ struct SceneDev {
     int stat, n_box, lds_box, goal_blocked;
     unsigned self_mask[kMaxDof + 1];
     float4 lbs[kMaxDof + 1];    // per link: bounding sphere of its spheres (link frame centre, radius)
-    int lds_lbr;                // float4 offset in LDS of the [d+1][O_pad] broad-phase thresholds
-    const float *lbr;           // (rho_l + r_o + kBroadMargin)^2, -1 for links without spheres
     const float4 *box;          // [n_box][4]
     const float4 *sph;          // [S]
     const float4 *goal;         // [S] world centres at q_g (x, y, z, |c|^2)
     const float *obs_r;         // [O] obstacle radii (the continuous check)
-    const float *R2;            // [S][O_pad]
+    const float *ro;            // [O_pad] obstacle radii (0 for padding obstacles)
+    float r_uni;                // the common obstacle radius, or -1 when radii differ
     const float4 *seg;          // [O_pad][n_seg][2]
     const float *seg_t;         // shared mode: [n_seg+1]; generic: [O_pad][n_seg+1]
 };
@@ -68,8 +67,6 @@ __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds)
     const int n = sc.O_pad * sc.n_seg * 2;
     for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = sc.seg[i];
     for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_sph + i] = sc.sph[i];
-    float *r2 = reinterpret_cast<float *>(lds + sc.lds_r2);
-    for (int i = threadIdx.x; i < sc.S * sc.O_pad; i += blockDim.x) r2[i] = sc.R2[i];
     if (sc.obs_mode == kObsGeneric) {
         float *lt = reinterpret_cast<float *>(lds + sc.lds_t);
         const int m = sc.O_pad * (sc.n_seg + 1);
@@ -78,10 +75,6 @@ __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds)
     if (sc.goal)
         for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_goal + i] = sc.goal[i];
     for (int i = threadIdx.x; i < 4 * sc.n_box; i += blockDim.x) lds[sc.lds_box + i] = sc.box[i];
-    if (sc.lbr) {
-        float *lt = reinterpret_cast<float *>(lds + sc.lds_lbr);
-        for (int i = threadIdx.x; i < (sc.d + 1) * sc.O_pad; i += blockDim.x) lt[i] = sc.lbr[i];
-    }
     __syncthreads();
 }
 
@@ -179,36 +172,33 @@ __device__ __forceinline__ int generic_segment(const SceneDev &sc, const float4 
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
-// Sphere s (centre c, a_s = |c|^2) against the OT obstacles of the tile:
-// a_s + b_o + c.n < (r_s + r_o)^2 for any o.  The radii row is read as float4
-// broadcasts; each compare's lane mask (the ballot of the active lanes) is
-// OR-ed on the scalar unit, so the loop is straight-line code with one add,
-// three FMAs and one compare per pair.  Returns the wave mask of hits.
-template <int OT>
-__device__ __forceinline__ uint64_t pair_hits(const float4 *lds, const SceneDev &sc, int s, int tile, float cx,
-                                              float cy, float cz, float as, const float *nx, const float *ny,
-                                              const float *nz, const float *bo) {
-    const float4 *r4 = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(lds + sc.lds_r2) +
-                                                        s * sc.O_pad + tile);
-    float r2[OT];
-#pragma unroll
-    for (int i = 0; i < OT / 4; ++i) {
-        const float4 v = r4[i];
-        r2[4 * i] = v.x;
-        r2[4 * i + 1] = v.y;
-        r2[4 * i + 2] = v.z;
-        r2[4 * i + 3] = v.w;
-    }
-    uint64_t m = 0;
+// Sphere (centre c, a_s = |c|^2, radius r_s) against the OT obstacles of the
+// tile.  With n = -2 o and A_o = |o|^2 - r_o^2 (per lane and obstacle, at the
+// lane's time), a pair collides iff
+//   A_o + c.n - 2 r r_o < r^2 - a_s,   r = r_s + eps,
+// which is |c - o|^2 < (r + r_o)^2 expanded.  The loop keeps the minimum of
+// the left side over the tile (three or four FMAs and half a min3 per pair,
+// no scalar-unit work); the result is that minimum minus the right side,
+// negative iff some pair collides.  With equal obstacle radii (UNI) the
+// r_o term moves to the right side.
+template <int OT, bool UNI>
+__device__ __forceinline__ float sphere_clear(const SceneDev &sc, float cx, float cy, float cz, float as, float r_s,
+                                              const float *nx, const float *ny, const float *nz, const float *A,
+                                              const float *ro) {
+    const float r = r_s + (float)kClearanceEps;
+    const float k = -2.0f * r;
+    float m = INFINITY;
 #pragma unroll
     for (int i = 0; i < OT; ++i) {
-        float v = as + bo[i];
-        v = fmaf(cx, nx[i], v);
+        float v = fmaf(cx, nx[i], A[i]);
         v = fmaf(cy, ny[i], v);
         v = fmaf(cz, nz[i], v);
-        m |= __ballot(v < r2[i]);
+        if (!UNI) v = fmaf(k, ro[i], v);
+        m = fminf(m, v);
     }
-    return m;
+    float rhs = fmaf(r, r, -as);
+    if (UNI) rhs = fmaf(-k, sc.r_uni, rhs);
+    return m - rhs;
 }
 
 // Squared distance from point c to fixed box b: offsets along the box axes,
@@ -326,71 +316,6 @@ __device__ __forceinline__ void static_pass(const SceneDev &sc, const float4 *ld
     }
 }
 
-// pair_hits restricted to the obstacles of the tile whose bit is set in the
-// wave-uniform mask `near` (the others are known to be clear of the link).
-template <int OT>
-__device__ __forceinline__ uint64_t pair_hits_near(const float4 *lds, const SceneDev &sc, int s, int tile, float cx,
-                                                   float cy, float cz, float as, const float *nx, const float *ny,
-                                                   const float *nz, const float *bo, uint32_t near) {
-    const float4 *r4 = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(lds + sc.lds_r2) +
-                                                        s * sc.O_pad + tile);
-    float r2[OT];
-#pragma unroll
-    for (int i = 0; i < OT / 4; ++i) {
-        const float4 v = r4[i];
-        r2[4 * i] = v.x;
-        r2[4 * i + 1] = v.y;
-        r2[4 * i + 2] = v.z;
-        r2[4 * i + 3] = v.w;
-    }
-    uint64_t m = 0;
-#pragma unroll
-    for (int i = 0; i < OT; ++i) {
-        if ((near >> i) & 1u) {
-            float v = as + bo[i];
-            v = fmaf(cx, nx[i], v);
-            v = fmaf(cy, ny[i], v);
-            v = fmaf(cz, nz[i], v);
-            m |= __ballot(v < r2[i]);
-        }
-    }
-    return m;
-}
-
-// Broad phase of a link against the OT obstacles of a tile: the obstacles
-// that come within rho_l + r_o + kBroadMargin of the link's bounding sphere
-// for some live lane of the wave (wave-uniform bit mask).  A clear obstacle
-// is at least kBroadMargin from every sphere of the link, where the exact
-// test could only report free.
-template <int OT>
-__device__ __forceinline__ uint32_t link_near(const float4 *lds, const SceneDev &sc, int l, int tile, const Frame &f,
-                                              bool alive, const float *nx, const float *ny, const float *nz,
-                                              const float *bo) {
-    float bx, by, bz, bs;
-    sphere_world(f, sc.lbs[l], bx, by, bz, bs);
-    const float4 *t4 = reinterpret_cast<const float4 *>(reinterpret_cast<const float *>(lds + sc.lds_lbr) +
-                                                        l * sc.O_pad + tile);
-    float thr[OT];
-#pragma unroll
-    for (int i = 0; i < OT / 4; ++i) {
-        const float4 v = t4[i];
-        thr[4 * i] = v.x;
-        thr[4 * i + 1] = v.y;
-        thr[4 * i + 2] = v.z;
-        thr[4 * i + 3] = v.w;
-    }
-    uint32_t near = 0;
-#pragma unroll
-    for (int i = 0; i < OT; ++i) {
-        float v = bs + bo[i];
-        v = fmaf(bx, nx[i], v);
-        v = fmaf(by, ny[i], v);
-        v = fmaf(bz, nz[i], v);
-        if (__ballot(alive && v < thr[i]) != 0) near |= 1u << i;
-    }
-    return near;
-}
-
 // Hit of the lane's state from the lane's accumulated pair masks.  A lane
 // knows its own bit exactly (its own ballots included it); with SPLIT > 1
 // the lanes of a state ran different numbers of sphere iterations, so their
@@ -404,9 +329,7 @@ __device__ __forceinline__ bool state_hit(uint64_t hm, int st_lane) {
 }
 
 // Does the lane's state (q, t) collide?  OT obstacles are held in registers
-// per tile; with BROAD the obstacles a link's bounding sphere clears for every
-// live lane of the wave are skipped for that link (exact, see link_near).
-// With SPLIT > 1 a state occupies SPLIT adjacent lanes (aligned)
+// per tile.  With SPLIT > 1 a state occupies SPLIT adjacent lanes (aligned)
 // and lane `part` of them tests the spheres s with s = part (mod SPLIT);
 // every lane composes the kinematic chain itself, and a state's hit is the OR
 // over its lanes, so all SPLIT lanes return the same answer.  This divides
@@ -419,7 +342,7 @@ __device__ __forceinline__ bool state_hit(uint64_t hm, int st_lane) {
 //           lower_mask holds the lanes of the lower states;
 //   !FIRST: stop as soon as any lane of its group has hit.
 // Every lane of the wave must call this (it contains ballots).
-template <int KIND, int OT, int OBS, bool FIRST, int SPLIT = 1, bool BROAD = false>
+template <int KIND, int OT, int OBS, bool FIRST, int SPLIT = 1>
 __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds, const float *q, float t, bool alive,
                                            uint64_t group_mask, uint64_t lower_mask, int part = 0) {
     static_assert(SPLIT == 1 || SPLIT == 2 || SPLIT == 4 || SPLIT == 8, "state split");
@@ -443,65 +366,67 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
     if (OBS == kObsShared) kseg = shared_segment(sc, t);
     for (int tile = 0; tile < sc.O_pad; tile += OT) {
         if (__ballot(alive) == 0) break;
-        float nx[OT], ny[OT], nz[OT], bo[OT];
+        float nx[OT], ny[OT], nz[OT], A[OT], ro[OT];
+#pragma unroll
+        for (int i = 0; i < OT; ++i) ro[i] = sc.ro[tile + i];
         if (alive) {
 #pragma unroll
             for (int i = 0; i < OT; ++i) {
                 const int o = tile + i;
                 const int k = (OBS == kObsShared) ? kseg : generic_segment(sc, lds, o, t);
                 obstacle_n(lds, sc.n_seg, o, k, t, nx[i], ny[i], nz[i]);
-                bo[i] = 0.25f * fmaf(nx[i], nx[i], fmaf(ny[i], ny[i], nz[i] * nz[i]));
+                A[i] = fmaf(0.25f, fmaf(nx[i], nx[i], fmaf(ny[i], ny[i], nz[i] * nz[i])), -ro[i] * ro[i]);
             }
         }
-        if (KIND == kTranslate) {
-            for (int s = part; s < sc.S; s += SPLIT) {
-                if (alive) {
-                    float cx, cy, cz, as;
-                    sphere_translate(sc, q, lds[sc.lds_sph + s], cx, cy, cz, as);
-                    hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
+        // one specialisation for equal obstacle radii, one for mixed radii
+        auto run = [&](auto uni_c) {
+            constexpr bool UNI = decltype(uni_c)::value;
+            if (KIND == kTranslate) {
+                float dmin = INFINITY;
+                for (int s = part; s < sc.S; s += SPLIT) {
+                    if (alive) {
+                        float cx, cy, cz, as;
+                        const float4 sp = lds[sc.lds_sph + s];
+                        sphere_translate(sc, q, sp, cx, cy, cz, as);
+                        dmin = fminf(dmin, sphere_clear<OT, UNI>(sc, cx, cy, cz, as, sp.w, nx, ny, nz, A, ro));
+                    }
                 }
-            }
-            hit = hit || state_hit<SPLIT>(hm, st_lane);
-            const uint64_t m = __ballot(hit);
-            if (FIRST) alive = alive && !hit && !(m & lower_mask);
-            else alive = alive && !(m & group_mask);
-        } else {
-            // world <- link frame
-            Frame f;
-            frame_identity(f);
+                hm |= __ballot(alive && dmin < 0.0f);
+                hit = hit || state_hit<SPLIT>(hm, st_lane);
+                const uint64_t m = __ballot(hit);
+                if (FIRST) alive = alive && !hit && !(m & lower_mask);
+                else alive = alive && !(m & group_mask);
+            } else {
+                // world <- link frame
+                Frame f;
+                frame_identity(f);
 #pragma unroll
-            for (int l = 0; l <= kMaxDof; ++l) {
-                if (l > sc.d) break;
-                if (l > 0 && alive) dh_compose(sc, l - 1, q[l - 1], f);
-                const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
-                if (s1 > s0 && __ballot(alive) != 0) {
-                    // this lane's spheres of the link: s = part (mod SPLIT)
-                    if (BROAD) {
-                        const uint32_t near = link_near<OT>(lds, sc, l, tile, f, alive, nx, ny, nz, bo);
-                        if (near != 0)
-                            for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
-                                if (alive) {
-                                    float cx, cy, cz, as;
-                                    sphere_world(f, lds[sc.lds_sph + s], cx, cy, cz, as);
-                                    hm |= pair_hits_near<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo, near);
-                                }
-                            }
-                    } else {
+                for (int l = 0; l <= kMaxDof; ++l) {
+                    if (l > sc.d) break;
+                    if (l > 0 && alive) dh_compose(sc, l - 1, q[l - 1], f);
+                    const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
+                    if (s1 > s0 && __ballot(alive) != 0) {
+                        // this lane's spheres of the link: s = part (mod SPLIT)
+                        float dmin = INFINITY;
                         for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
                             if (alive) {
                                 float cx, cy, cz, as;
-                                sphere_world(f, lds[sc.lds_sph + s], cx, cy, cz, as);
-                                hm |= pair_hits<OT>(lds, sc, s, tile, cx, cy, cz, as, nx, ny, nz, bo);
+                                const float4 sp = lds[sc.lds_sph + s];
+                                sphere_world(f, sp, cx, cy, cz, as);
+                                dmin = fminf(dmin, sphere_clear<OT, UNI>(sc, cx, cy, cz, as, sp.w, nx, ny, nz, A, ro));
                             }
                         }
+                        hm |= __ballot(alive && dmin < 0.0f);
+                        hit = hit || state_hit<SPLIT>(hm, st_lane);
+                        const uint64_t m = __ballot(hit);
+                        if (FIRST) alive = alive && !hit && !(m & lower_mask);
+                        else alive = alive && !(m & group_mask);
                     }
-                    hit = hit || state_hit<SPLIT>(hm, st_lane);
-                    const uint64_t m = __ballot(hit);
-                    if (FIRST) alive = alive && !hit && !(m & lower_mask);
-                    else alive = alive && !(m & group_mask);
                 }
             }
-        }
+        };
+        if (sc.r_uni >= 0.0f) run(std::true_type{});
+        else run(std::false_type{});
     }
     // time-independent terms for the lanes still undecided
     if (KIND == kDHStatic && __ballot(alive) != 0)
@@ -532,25 +457,30 @@ __device__ __forceinline__ bool goal_hits(const SceneDev &sc, const float4 *lds,
     if (OBS == kObsShared) kseg = shared_segment(sc, t);
     for (int tile = 0; tile < sc.O_pad; tile += OT) {
         if (__ballot(alive) == 0) break;
-        float nx[OT], ny[OT], nz[OT], bo[OT];
+        float nx[OT], ny[OT], nz[OT], A[OT], ro[OT];
+#pragma unroll
+        for (int i = 0; i < OT; ++i) ro[i] = sc.ro[tile + i];
         if (alive) {
 #pragma unroll
             for (int i = 0; i < OT; ++i) {
                 const int o = tile + i;
                 const int k = (OBS == kObsShared) ? kseg : generic_segment(sc, lds, o, t);
                 obstacle_n(lds, sc.n_seg, o, k, t, nx[i], ny[i], nz[i]);
-                bo[i] = 0.25f * fmaf(nx[i], nx[i], fmaf(ny[i], ny[i], nz[i] * nz[i]));
+                A[i] = fmaf(0.25f, fmaf(nx[i], nx[i], fmaf(ny[i], ny[i], nz[i] * nz[i])), -ro[i] * ro[i]);
             }
         }
         for (int l = 0; l <= sc.d; ++l) {
             const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
             if (s1 > s0 && __ballot(alive) != 0) {
+                float dmin = INFINITY;
                 for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
                     if (alive) {
                         const float4 c = lds[sc.lds_goal + s];
-                        hm |= pair_hits<OT>(lds, sc, s, tile, c.x, c.y, c.z, c.w, nx, ny, nz, bo);
+                        const float r_s = lds[sc.lds_sph + s].w;
+                        dmin = fminf(dmin, sphere_clear<OT, false>(sc, c.x, c.y, c.z, c.w, r_s, nx, ny, nz, A, ro));
                     }
                 }
+                hm |= __ballot(alive && dmin < 0.0f);
                 hit = hit || state_hit<SPLIT>(hm, st_lane);
                 alive = alive && !hit;
             }

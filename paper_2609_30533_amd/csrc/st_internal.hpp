@@ -155,12 +155,11 @@ struct st_problem {
     double t_min = 0, t_max = 0, v_max = 0, Lg = 0, L = 0;
     st::SceneDev sc{};
     float4 *d_sph = nullptr;
-    float *d_R2 = nullptr;
+    float *d_ro = nullptr;     // obstacle radii [O_pad]
     float4 *d_seg = nullptr;
     float4 *d_goal = nullptr;  // sphere centres at q_g
     float *d_obs_r = nullptr;  // obstacle radii
     float4 *d_box = nullptr;   // static boxes, 4 rows each
-    float *d_lbr = nullptr;    // broad-phase thresholds [d+1][O_pad]
     float *d_segt = nullptr;
     // goal grid and windows
     int64_t k_lo = 0, k_hi = -1;
