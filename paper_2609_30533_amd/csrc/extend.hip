@@ -770,107 +770,16 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
 // ---------------------------------------------------------------------------
 
 
-__device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, float c2, int w2) {
-    if (u1 != u2) return u1 < u2;
-    if (c1 != c2) return c1 < c2;
-    return (uint32_t)w1 < (uint32_t)w2;
-}
-
-template <bool MULTI>
-__global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishArgs *av) {
-    __shared__ float sU[1024], sC[1024];
-    __shared__ int sW[1024];
-    const PublishArgs &a = MULTI ? av[blockIdx.y] : a0;
-    const int tid = threadIdx.x;
-    const Work &k = a.w;
-    float bu = INFINITY, bc = INFINITY;
-    int bw = -1;
-    for (int64_t w = tid; w < a.B; w += blockDim.x) {
-        const bool ok = k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w] && k.br_free[w];
-        if (!ok) {
-            k.Up[w] = INFINITY;
-            k.Cp[w] = INFINITY;
-        } else if (lex_less(k.Up[w], k.Cp[w], (int)w, bu, bc, bw)) {
-            bu = k.Up[w];
-            bc = k.Cp[w];
-            bw = (int)w;
-        }
-    }
-    sU[tid] = bu;
-    sC[tid] = bc;
-    sW[tid] = bw;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (tid < s && lex_less(sU[tid + s], sC[tid + s], sW[tid + s], sU[tid], sC[tid], sW[tid])) {
-            sU[tid] = sU[tid + s];
-            sC[tid] = sC[tid + s];
-            sW[tid] = sW[tid + s];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        PlanDev *pl = a.pl;
-        const int w = sW[0];
-        // every load before the first store
-        const float U0 = pl->U, C0 = pl->C;
-        const int32_t it = pl->iter, fi = pl->first_iter;
-        int8_t dw = 0;
-        int32_t ni = -1, bw = -1;
-        if (w >= 0) {
-            dw = a.dir[w];
-            ni = k.new_idx[w];
-            bw = k.bridge[w];
-        }
-        if (w >= 0 && (sU[0] < U0 || (sU[0] == U0 && sC[0] < C0))) {
-            pl->improved = sU[0] < U0 ? 2 : 1;
-            pl->U = sU[0];
-            pl->C = sC[0];
-            pl->inc_f = dw == 0 ? ni : bw;
-            pl->inc_b = dw == 0 ? bw : ni;
-            if (fi < 0) pl->first_iter = it;
-        }
-        pl->iter = it + 1;
-    }
-    // optional caller outputs
-    const st_extend_out &o = a.out;
-    const int W = 0;
-    (void)W;
-    for (int64_t w = tid; w < a.B; w += blockDim.x) {
-        if (o.status) o.status[w] = k.status[w];
-        if (o.parent) o.parent[w] = k.parent[w];
-        if (o.new_idx) o.new_idx[w] = k.new_idx[w];
-        if (o.bridge) o.bridge[w] = k.bridge[w];
-        if (o.bridge_ok) o.bridge_ok[w] = (k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w]) ? k.br_free[w] : 0;
-        if (o.Up) o.Up[w] = k.Up[w];
-        if (o.Cp) o.Cp[w] = k.Cp[w];
-    }
-}
-
-struct XnewOutArgs {
-    int64_t B;
-    int32_t d;
-    const int8_t *status;
-    const float *xnew;
-    float *out;
-};
-
-__global__ void k_xnew_out(XnewOutArgs a) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.B) return;
-    const bool adv = a.status[w] >= ST_STATUS_ADVANCED;
-    for (int j = 0; j <= a.d; ++j) a.out[(int64_t)j * a.B + w] = adv ? a.xnew[w * (a.d + 1) + j] : 0.f;
-}
-
 // ---------------------------------------------------------------------------
 // a8 / a9: allocation update after a strict drop of U
 // ---------------------------------------------------------------------------
 
 
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_roots(RootsArgs a0, const RootsArgs *av) {
+// Runs at the end of the publish block: every thread of the block calls it,
+// after a barrier that makes the incumbent update visible.
+__device__ __forceinline__ void roots_body(const RootsArgs &a) {
     __shared__ int cand[kMaxGroups], assign[kMaxGroups], donor[kMaxGroups];
     __shared__ int s_kend;
-    const RootsArgs &a = MULTI ? av[blockIdx.y] : a0;
     PlanDev *pl = a.pl;
     if (pl->improved != 2) return;
     const int tid = threadIdx.x, N = a.N;
@@ -961,6 +870,101 @@ __global__ __launch_bounds__(256) void k_roots(RootsArgs a0, const RootsArgs *av
             if (pl->slot_active[s]) pl->active_list[na++] = s;
         pl->n_active = na;
     }
+}
+
+__device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, float c2, int w2) {
+    if (u1 != u2) return u1 < u2;
+    if (c1 != c2) return c1 < c2;
+    return (uint32_t)w1 < (uint32_t)w2;
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishArgs *av, RootsArgs r0,
+                                                  const RootsArgs *rv) {
+    __shared__ float sU[1024], sC[1024];
+    __shared__ int sW[1024];
+    const PublishArgs &a = MULTI ? av[blockIdx.y] : a0;
+    const int tid = threadIdx.x;
+    const Work &k = a.w;
+    float bu = INFINITY, bc = INFINITY;
+    int bw = -1;
+    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+        const bool ok = k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w] && k.br_free[w];
+        if (!ok) {
+            k.Up[w] = INFINITY;
+            k.Cp[w] = INFINITY;
+        } else if (lex_less(k.Up[w], k.Cp[w], (int)w, bu, bc, bw)) {
+            bu = k.Up[w];
+            bc = k.Cp[w];
+            bw = (int)w;
+        }
+    }
+    sU[tid] = bu;
+    sC[tid] = bc;
+    sW[tid] = bw;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if (tid < s && lex_less(sU[tid + s], sC[tid + s], sW[tid + s], sU[tid], sC[tid], sW[tid])) {
+            sU[tid] = sU[tid + s];
+            sC[tid] = sC[tid + s];
+            sW[tid] = sW[tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        PlanDev *pl = a.pl;
+        const int w = sW[0];
+        // every load before the first store
+        const float U0 = pl->U, C0 = pl->C;
+        const int32_t it = pl->iter, fi = pl->first_iter;
+        int8_t dw = 0;
+        int32_t ni = -1, bw = -1;
+        if (w >= 0) {
+            dw = a.dir[w];
+            ni = k.new_idx[w];
+            bw = k.bridge[w];
+        }
+        if (w >= 0 && (sU[0] < U0 || (sU[0] == U0 && sC[0] < C0))) {
+            pl->improved = sU[0] < U0 ? 2 : 1;
+            pl->U = sU[0];
+            pl->C = sC[0];
+            pl->inc_f = dw == 0 ? ni : bw;
+            pl->inc_b = dw == 0 ? bw : ni;
+            if (fi < 0) pl->first_iter = it;
+        }
+        pl->iter = it + 1;
+    }
+    // optional caller outputs
+    const st_extend_out &o = a.out;
+    const int W = 0;
+    (void)W;
+    for (int64_t w = tid; w < a.B; w += blockDim.x) {
+        if (o.status) o.status[w] = k.status[w];
+        if (o.parent) o.parent[w] = k.parent[w];
+        if (o.new_idx) o.new_idx[w] = k.new_idx[w];
+        if (o.bridge) o.bridge[w] = k.bridge[w];
+        if (o.bridge_ok) o.bridge_ok[w] = (k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w]) ? k.br_free[w] : 0;
+        if (o.Up) o.Up[w] = k.Up[w];
+        if (o.Cp) o.Cp[w] = k.Cp[w];
+    }
+    // a8 / a9 in the same block (no launch of its own)
+    __syncthreads();
+    roots_body(MULTI ? rv[blockIdx.y] : r0);
+}
+
+struct XnewOutArgs {
+    int64_t B;
+    int32_t d;
+    const int8_t *status;
+    const float *xnew;
+    float *out;
+};
+
+__global__ void k_xnew_out(XnewOutArgs a) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.B) return;
+    const bool adv = a.status[w] >= ST_STATUS_ADVANCED;
+    for (int j = 0; j <= a.d; ++j) a.out[(int64_t)j * a.B + w] = adv ? a.xnew[w * (a.d + 1) + j] : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -1348,15 +1352,13 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     prof_mark(p, kStBridgeEdge, s);
     ST_HIP(launch_edge_args(a.edge_br, s));
     prof_mark(p, kStPublish, s);
-    k_publish<false><<<1, 1024, 0, s>>>(a.publish, nullptr);
+    k_publish<false><<<1, 1024, 0, s>>>(a.publish, nullptr, a.roots, nullptr);
     ST_HIP(hipGetLastError());
     if (out && out->xnew) {
         XnewOutArgs xa{B, p->d, p->work.status, p->work.xnew, out->xnew};
         k_xnew_out<<<blocks, 256, 0, s>>>(xa);
         ST_HIP(hipGetLastError());
     }
-    k_roots<false><<<1, 256, 0, s>>>(a.roots, nullptr);
-    ST_HIP(hipGetLastError());
     prof_mark(p, kStEnd, s);
     return ST_OK;
 }
@@ -1399,8 +1401,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     for (const BatchClass &c : L.classes)
         ST_HIP(launch_edge_items_multi(c.key, c.split_br, L.edge_br, c.members, c.n, c.nb_items_br, c.lds, s));
     ST_HIP(launch_edge_finish_multi(L.edge_br, L.P, L.nb_edge, s));
-    k_publish<true><<<dim3(1, L.P), 1024, 0, s>>>(PublishArgs{}, L.publish);
-    k_roots<true><<<dim3(1, L.P), 256, 0, s>>>(RootsArgs{}, L.roots);
+    k_publish<true><<<dim3(1, L.P), 1024, 0, s>>>(PublishArgs{}, L.publish, RootsArgs{}, L.roots);
     ST_HIP(hipGetLastError());
     return ST_OK;
 }
