@@ -195,7 +195,13 @@ typedef struct st_info {
 /* Validate and copy the description, upload the scene, allocate the trees on
  * the current device, compute the goal grid valid(q_g, k dt) (Eq. 5) and the
  * initial allocation (interval-root partition or recycling roots).  The handle
- * owns all device memory.  Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP. */
+ * owns all device memory.  Errors: ST_EINVAL, ST_ENOMEM, ST_EHIP.  Besides the
+ * per-field limits, the scene staged per block must fit in 64 KB of LDS:
+ * 32 B per obstacle (rounded up to the obstacle tile of 4, 8 or 16) and
+ * trajectory segment (max_waypoints - 1, at least 1), 32 B per sphere, 64 B per
+ * box, and 4 B per obstacle and waypoint when the obstacles' waypoint times
+ * differ; a larger scene is ST_EINVAL (e.g. 64 obstacles with 16 waypoints fit,
+ * 64 with 32 do not). */
 int st_problem_create(const st_problem_desc *desc, st_problem **out);
 
 /* Release the handle and its device memory.  Null-safe. */
