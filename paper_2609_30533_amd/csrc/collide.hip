@@ -334,32 +334,37 @@ __device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
 }
 
 // ---------------------------------------------------------------------------
-// Short edges, flattened: one wave per block takes kFlatEdges consecutive
-// edges, lays their states end to end (edge after edge, state order inside
-// an edge) over its 64 lanes in rounds, and decides them completely: state
-// count, checks, free / first hit and the work counters, in one kernel.  A
-// lane skips a state above a hit already found for its edge; within a round
-// the lanes of one edge form the group of the FIRST rule, so the least
-// colliding index is exact.  Meant for edges of bounded length (extensions):
-// a long edge would serialise its rounds in one wave.
+// Short edges, flattened: a block of kFlatWaves waves takes kFlatWaves x
+// a.flat consecutive edges, lays their states end to end (edge after edge,
+// state order inside an edge) in rounds of 64, and decides them completely:
+// state count, checks, free / first hit and the work counters, in one kernel.
+// The rounds are dealt to the block's waves in turn (wave w takes rounds w,
+// w + kFlatWaves, ...), so the state checks spread evenly over the CU's SIMDs
+// whatever the edges' lengths; the scene is staged into LDS once per block.
+// A lane skips a state above a hit already found for its edge (by any wave);
+// within a round the lanes of one edge form the group of the FIRST rule, and
+// hits merge with an atomic minimum, so the least colliding index is exact.
+// Meant for edges of bounded length (extensions).
 // ---------------------------------------------------------------------------
 
-constexpr int kFlatEdges = 8;  // edges per block at most (a.flat of them)
+constexpr int kFlatEdges = 8;  // edges per wave at most (a.flat of them)
+constexpr int kFlatWaves = 4;  // waves per block
+constexpr int kFlatBlockEdges = kFlatEdges * kFlatWaves;
 
 template <int KIND, int OT, int OBS>
 __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, int bx) {
-    __shared__ float s_A[kFlatEdges][kMaxDof + 1], s_B[kFlatEdges][kMaxDof + 1];
-    __shared__ int32_t s_off[kFlatEdges + 1], s_n[kFlatEdges], s_hit[kFlatEdges];
+    __shared__ float s_A[kFlatBlockEdges][kMaxDof + 1], s_B[kFlatBlockEdges][kMaxDof + 1];
+    __shared__ int32_t s_off[kFlatBlockEdges + 1], s_n[kFlatBlockEdges], s_hit[kFlatBlockEdges];
     const SceneDev &sc = a.sc;
     const int d = sc.d, W = d + 1;
-    const int lane = threadIdx.x;  // one wave per block
-    const int EB = a.flat;
-    const int64_t e0 = (int64_t)bx * EB;
+    const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int NE = a.flat * kFlatWaves;  // edges of this block
+    const int64_t e0 = (int64_t)bx * NE;
     stage_obstacles(sc, lds);
-    if (lane < kFlatEdges) {
-        const int64_t e = e0 + lane;
+    if (tid < kFlatBlockEdges) {
+        const int64_t e = e0 + tid;
         int32_t n = -1;
-        if (lane < EB && e < a.E && !(a.valid && !a.valid[e])) {
+        if (tid < NE && e < a.E && !(a.valid && !a.valid[e])) {
             const float *A = a.xa + e * W, *B = a.xb + e * W;
             if (A[d] > B[d]) { const float *tmp = A; A = B; B = tmp; }
             double D2 = 0.0;
@@ -373,33 +378,37 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
             if (nn > (1ll << 30)) nn = 1ll << 30;
             n = (int32_t)nn;
             for (int j = 0; j <= kMaxDof; ++j) {
-                s_A[lane][j] = j <= d ? A[j] : 0.f;
-                s_B[lane][j] = j <= d ? B[j] : 0.f;
+                s_A[tid][j] = j <= d ? A[j] : 0.f;
+                s_B[tid][j] = j <= d ? B[j] : 0.f;
             }
         }
-        s_n[lane] = n;
-        s_hit[lane] = kNoHit;
+        s_n[tid] = n;
+        s_hit[tid] = kNoHit;
     }
     __syncthreads();
-    if (lane == 0) {
-        int acc = 0;
-        for (int i = 0; i < kFlatEdges; ++i) {
-            s_off[i] = acc;
-            acc += s_n[i] >= 0 ? s_n[i] + 1 : 0;
-        }
-        s_off[kFlatEdges] = acc;
-    }
-    __syncthreads();
-    const int total = s_off[kFlatEdges];
-    for (int base = 0; base < total; base += 64) {
-        const int g = base + lane;
-        int i = 0;
+    if (tid < 64) {
+        // exclusive prefix of the state counts (kFlatBlockEdges <= 64 lanes)
+        const int c = tid < kFlatBlockEdges ? (s_n[tid] >= 0 ? s_n[tid] + 1 : 0) : 0;
+        int incl = c;
 #pragma unroll
-        for (int k = 1; k < kFlatEdges; ++k) i += g >= s_off[k] ? 1 : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int v = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += v;
+        }
+        if (tid < kFlatBlockEdges) s_off[tid] = incl - c;
+        if (tid == kFlatBlockEdges - 1) s_off[kFlatBlockEdges] = incl;
+    }
+    __syncthreads();
+    const int total = s_off[kFlatBlockEdges];
+    for (int base = wv * 64; base < total; base += 64 * kFlatWaves) {
+        const int g = base + lane;
+        // edge of state g: the number of edge starts at or below g, minus one
+        int i = 0;
+        for (int k = 1; k < kFlatBlockEdges; ++k) i += g >= s_off[k] ? 1 : 0;
         const int j = g - s_off[i];
         const int32_t n = s_n[i];
         // a state above a known hit of its edge is not needed
-        const bool act = g < total && j <= s_hit[i];
+        const bool act = g < total && j <= __atomic_load_n(&s_hit[i], __ATOMIC_RELAXED);
         // lanes of this edge in this round: its group for the FIRST rule
         const int lo = max(s_off[i] - base, 0), hi = min(s_off[i + 1] - base, 64);
         const uint64_t seg = (hi >= 64 ? ~0ull : ((1ull << hi) - 1ull)) & ~((1ull << lo) - 1ull);
@@ -422,15 +431,15 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
         }
         const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, q, t, act, seg, lower);
         if (hit && act) atomicMin(&s_hit[i], j);
-        __syncthreads();
     }
+    __syncthreads();
     // results and work counters
     unsigned long long states = 0, edges = 0;
-    if (lane < EB) {
-        const int64_t e = e0 + lane;
-        const int32_t n = s_n[lane];
+    if (tid < NE && tid < kFlatBlockEdges) {
+        const int64_t e = e0 + tid;
+        const int32_t n = s_n[tid];
         if (e < a.E && n >= 0) {
-            const int32_t h = s_hit[lane];
+            const int32_t h = s_hit[tid];
             const bool fr = h == kNoHit;
             a.free_out[e] = fr ? 1 : 0;
             if (a.first_hit) a.first_hit[e] = fr ? -1 : h;
@@ -438,7 +447,7 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
             edges = 1;
         }
     }
-    if (a.work) {
+    if (a.work && wv == 0) {
         for (int o = 32; o > 0; o >>= 1) {
             states += __shfl_down(states, o, 64);
             edges += __shfl_down(edges, o, 64);
@@ -451,16 +460,16 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
 }
 
 template <int KIND, int OT, int OBS>
-__global__ __launch_bounds__(64) void k_edge_flat(EdgeArgs a) {
+__global__ __launch_bounds__(64 * kFlatWaves) void k_edge_flat(EdgeArgs a) {
     extern __shared__ float4 lds[];
     edge_flat_body<KIND, OT, OBS>(a, lds, blockIdx.x);
 }
 
 template <int KIND, int OT, int OBS>
-__global__ __launch_bounds__(64) void k_edge_flat_multi(const EdgeArgs *av, const int32_t *members) {
+__global__ __launch_bounds__(64 * kFlatWaves) void k_edge_flat_multi(const EdgeArgs *av, const int32_t *members) {
     extern __shared__ float4 lds[];
     const EdgeArgs &a = av[members[blockIdx.y]];
-    if ((int64_t)blockIdx.x * a.flat >= a.E) return;
+    if ((int64_t)blockIdx.x * kFlatWaves * a.flat >= a.E) return;
     edge_flat_body<KIND, OT, OBS>(a, lds, blockIdx.x);
 }
 
@@ -613,7 +622,8 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
 }
 
 int flat_blocks(int64_t E, int edges_per_block) {
-    return (int)((E + edges_per_block - 1) / edges_per_block);
+    const int64_t per = (int64_t)edges_per_block * kFlatWaves;
+    return (int)((E + per - 1) / per);
 }
 
 hipError_t launch_check_edges(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
@@ -630,7 +640,7 @@ hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
     if (a.flat) {
         dispatch_scene(a.sc, [&](auto kind, auto ot, auto obs) {
             k_edge_flat<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
-                <<<dim3(flat_blocks(a.E, a.flat)), dim3(64), scene_lds_bytes(a.sc), s>>>(a);
+                <<<dim3(flat_blocks(a.E, a.flat)), dim3(64 * kFlatWaves), scene_lds_bytes(a.sc), s>>>(a);
         });
         return hipGetLastError();
     }
@@ -649,7 +659,7 @@ hipError_t launch_edge_flat_multi(const SceneDev &cls, const EdgeArgs *d_args, c
                                   int n_members, int max_blocks, size_t lds, hipStream_t s) {
     dispatch_scene(cls, [&](auto kind, auto ot, auto obs) {
         k_edge_flat_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
-            <<<dim3(max_blocks, n_members), dim3(64), lds, s>>>(d_args, d_members);
+            <<<dim3(max_blocks, n_members), dim3(64 * kFlatWaves), lds, s>>>(d_args, d_members);
     });
     return hipGetLastError();
 }
