@@ -421,9 +421,9 @@ int st_set_tuning(st_problem *p, int32_t obstacle_tile, int32_t lanes_extension,
 int st_set_state_split(st_problem *p, int32_t split_extension, int32_t split_bridge, int32_t split_check);
 
 /* Extension edges (at most ceil(sqrt(2) eta / h) + 1 states) are checked by a
- * flattened one-kernel path: a block of four waves takes 4 x `edges_per_block`
- * consecutive edges (1..8 per wave), lays their states end to end and deals
- * them to its waves in rounds of 64.
+ * flattened one-kernel path: a block of eight waves takes 4 x `edges_per_block`
+ * consecutive edges (edges_per_block 1..8), lays their states end to end and
+ * deals them to its waves in rounds of 64.
  * 0 selects the chunked path that bridges and st_check_edges use.  Results do
  * not depend on this.  Default 4.  Synchronous; drops captured graphs. */
 int st_set_flat_extension(st_problem *p, int32_t edges_per_block);

@@ -334,12 +334,13 @@ __device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
 }
 
 // ---------------------------------------------------------------------------
-// Short edges, flattened: a block of kFlatWaves waves takes kFlatWaves x
+// Short edges, flattened: a block of kFlatWaves waves takes kFlatGroups x
 // a.flat consecutive edges, lays their states end to end (edge after edge,
 // state order inside an edge) in rounds of 64, and decides them completely:
 // state count, checks, free / first hit and the work counters, in one kernel.
 // The rounds are dealt to the block's waves in turn (wave w takes rounds w,
 // w + kFlatWaves, ...), so the state checks spread evenly over the CU's SIMDs
+// (two waves each, so that one's memory waits overlap the other's arithmetic)
 // whatever the edges' lengths; the scene is staged into LDS once per block.
 // A lane skips a state above a hit already found for its edge (by any wave);
 // within a round the lanes of one edge form the group of the FIRST rule, and
@@ -348,8 +349,9 @@ __device__ __forceinline__ void edge_finish_body(const EdgeArgs &a, int bx) {
 // ---------------------------------------------------------------------------
 
 constexpr int kFlatEdges = 8;  // edges per wave at most (a.flat of them)
-constexpr int kFlatWaves = 4;  // waves per block
-constexpr int kFlatBlockEdges = kFlatEdges * kFlatWaves;
+constexpr int kFlatWaves = 8;  // waves per block (two per SIMD)
+constexpr int kFlatGroups = 4;  // the edges of a block: kFlatGroups x a.flat
+constexpr int kFlatBlockEdges = kFlatEdges * kFlatGroups;
 
 template <int KIND, int OT, int OBS>
 __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, int bx) {
@@ -358,7 +360,7 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
     const SceneDev &sc = a.sc;
     const int d = sc.d, W = d + 1;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
-    const int NE = a.flat * kFlatWaves;  // edges of this block
+    const int NE = a.flat * kFlatGroups;  // edges of this block
     const int64_t e0 = (int64_t)bx * NE;
     stage_obstacles(sc, lds);
     if (tid < kFlatBlockEdges) {
@@ -469,7 +471,7 @@ template <int KIND, int OT, int OBS>
 __global__ __launch_bounds__(64 * kFlatWaves) void k_edge_flat_multi(const EdgeArgs *av, const int32_t *members) {
     extern __shared__ float4 lds[];
     const EdgeArgs &a = av[members[blockIdx.y]];
-    if ((int64_t)blockIdx.x * kFlatWaves * a.flat >= a.E) return;
+    if ((int64_t)blockIdx.x * kFlatGroups * a.flat >= a.E) return;
     edge_flat_body<KIND, OT, OBS>(a, lds, blockIdx.x);
 }
 
@@ -622,7 +624,7 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
 }
 
 int flat_blocks(int64_t E, int edges_per_block) {
-    const int64_t per = (int64_t)edges_per_block * kFlatWaves;
+    const int64_t per = (int64_t)edges_per_block * kFlatGroups;
     return (int)((E + per - 1) / per);
 }
 

@@ -408,10 +408,22 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
                     if (s1 > s0 && __ballot(alive) != 0) {
                         // this lane's spheres of the link: s = part (mod SPLIT)
                         float dmin = INFINITY;
-                        for (int s = s0 + ((part - s0) & (SPLIT - 1)); s < s1; s += SPLIT) {
-                            if (alive) {
-                                float cx, cy, cz, as;
+                        if (alive) {
+                            // two spheres per step: both offset reads are in flight together
+                            const int first = s0 + ((part - s0) & (SPLIT - 1));
+                            int s = first;
+                            for (; s + SPLIT < s1; s += 2 * SPLIT) {
                                 const float4 sp = lds[sc.lds_sph + s];
+                                const float4 sq = lds[sc.lds_sph + s + SPLIT];
+                                float cx, cy, cz, as, ex, ey, ez, bs;
+                                sphere_world(f, sp, cx, cy, cz, as);
+                                sphere_world(f, sq, ex, ey, ez, bs);
+                                dmin = fminf(dmin, sphere_clear<OT, UNI>(sc, cx, cy, cz, as, sp.w, nx, ny, nz, A, ro));
+                                dmin = fminf(dmin, sphere_clear<OT, UNI>(sc, ex, ey, ez, bs, sq.w, nx, ny, nz, A, ro));
+                            }
+                            if (s < s1) {
+                                const float4 sp = lds[sc.lds_sph + s];
+                                float cx, cy, cz, as;
                                 sphere_world(f, sp, cx, cy, cz, as);
                                 dmin = fminf(dmin, sphere_clear<OT, UNI>(sc, cx, cy, cz, as, sp.w, nx, ny, nz, A, ro));
                             }
