@@ -570,7 +570,9 @@ int st_problem_create(const st_problem_desc *D, st_problem **out) {
         while ((1 << shift) < n_typ && shift < 6) ++shift;
         p->tune_ext = shift;
         p->tune_api = shift;
-        p->tune_br = 6;
+        // bridges mostly collide within their first few states: short chunks
+        // let one wave take several bridges
+        p->tune_br = 4;
     }
     if ((rc = build_scene(p, D)) != ST_OK || (rc = build_goal_grid(p)) != ST_OK || (rc = alloc_trees(p)) != ST_OK ||
         (rc = init_state(p)) != ST_OK || (rc = work_reserve(p, p->prm.batch)) != ST_OK) {

@@ -230,7 +230,6 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     const EdgeBufs &eb = a.eb;
     const float *__restrict__ xa = a.xa;
     const float *__restrict__ xb = a.xb;
-    stage_obstacles(sc, lds);
     int32_t pre[17];
     pre[0] = 0;
     for (int r = 0; r < eb.mmax; ++r) pre[r + 1] = pre[r] + eb.cnt[r * kCntStride];
@@ -239,6 +238,10 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     const int lpe_shift = a.lpe_shift;
     const int lpe = 1 << lpe_shift;
     const int G = 64 >> lpe_shift;
+    // a block without any item leaves before staging the scene (the grid is
+    // sized for the largest launch; the item count is known only here)
+    if ((int64_t)bx * (blockDim.x >> 6) * G >= total) return;
+    stage_obstacles(sc, lds);
     const int sub = lane & (lpe - 1), gsel = lane >> lpe_shift;
     // SPLIT lanes per state: states per chunk ls, the lane's state slot and part
     const int ls = lpe / SPLIT, slot = sub / SPLIT, part = sub & (SPLIT - 1);

@@ -179,7 +179,7 @@ struct st_problem {
     // captured iterations: [0] one iteration, [1] four iterations
     bool use_graphs = true;
     // lanes per edge chunk (log2) for extension, bridge and st_check_edges launches
-    int tune_ext = 5, tune_br = 6, tune_api = 5;
+    int tune_ext = 5, tune_br = 4, tune_api = 5;
     // lanes per state (log2) for the same three launches; -1 chooses by size
     int split_ext = -1, split_br = -1, split_api = -1;
     // extension edges per block of the flattened path (0: chunked item path)
