@@ -259,7 +259,7 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
     // R consecutive workers per thread and pass, all loads before the stores
     constexpr int R = 4;
     const bool one_pass = a.B <= (int64_t)blockDim.x * R;
-    int sets[R];
+    int sets[R], pos[R];
     for (int64_t base = 0; base < a.B; base += (int64_t)blockDim.x * R) {
         uint8_t f[R];
         int8_t dr[R];
@@ -300,8 +300,9 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
             }
             sets[r] = w < a.B ? set : -1;
         }
+        // positions inside the sets (kept for the single-pass case)
 #pragma unroll
-        for (int r = 0; r < R; ++r) wave_bucket_add(cnt, sets[r]);
+        for (int r = 0; r < R; ++r) pos[r] = wave_bucket_add(cnt, sets[r]);
     }
     __syncthreads();
     if (tid == 0) {
@@ -327,12 +328,11 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
     }
     __syncthreads();
     if (one_pass) {
-        // the sets are still in registers
+        // the sets and the positions inside them are still in registers
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t w = (int64_t)tid * R + r;
-            const int pos = wave_bucket_add(cur, sets[r]);
-            if (sets[r] >= 0) a.order[pos] = (int32_t)w;
+            if (sets[r] >= 0) a.order[cur[sets[r]] + pos[r]] = (int32_t)w;
         }
     } else {
         for (int64_t base = 0; base < a.B; base += blockDim.x) {
