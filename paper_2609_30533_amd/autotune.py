@@ -1,14 +1,15 @@
 """Autotuner of the many-problem launch: samples per problem per iteration
-and lanes per edge chunk, chosen per problem class and cached as JSON.
+and lanes per bridge chunk, chosen per problem class and cached as JSON.
 
 A class is (degrees of freedom, obstacle-count bucket).  For each class the
 tuner draws tuning problems of that class (seeds disjoint from evaluation
 seeds), plans them as one batch under each candidate setting for a fixed
 device-time budget, and scores a setting by the summed time to first
 solution (an unsolved problem counts the whole budget).  It searches the
-sample count first with 32 lanes per extension edge, then the lane count at
-the best sample count.  Everything it runs is the library's planner; this
-module only orders the experiments and keeps the table.
+sample count first with 16 lanes per bridge chunk, then the lane count at
+the best sample count.  (Extension edges take the flattened path, where the
+lanes per chunk play no part.)  Everything it runs is the library's planner;
+this module only orders the experiments and keeps the table.
 """
 from __future__ import annotations
 
@@ -24,10 +25,11 @@ from . import scenes
 from .lib import Batch, Problem
 
 SAMPLES = (64, 128, 256, 512)
-LANES = (16, 32, 64)
+LANES = (8, 16, 32, 64)
+LANES_FIRST = 16
 OBS_BUCKETS = (8, 16, 32, 64)
 TUNE_SEED0 = 3_000_000
-DEFAULT = {"samples": 128, "lanes_extension": 32, "lanes_bridge": 64}
+DEFAULT = {"samples": 128, "lanes_extension": 32, "lanes_bridge": 16}
 
 
 def obs_bucket(n_obs: int) -> int:
@@ -68,7 +70,7 @@ def score(problems, samples, lanes, budget_ms):
         p.params.batch = samples
     gps = [Problem(p, problem_id=i) for i, p in enumerate(problems)]
     for g in gps:
-        g.set_tuning(lanes_extension=lanes, lanes_bridge=64)
+        g.set_tuning(lanes_extension=DEFAULT["lanes_extension"], lanes_bridge=lanes)
     b = Batch(gps)
     r = b.plan(max_ms=budget_ms, stop_at_first=True)
     fm = np.where(np.isfinite(r["first_ms"]), r["first_ms"], budget_ms)
@@ -86,18 +88,19 @@ def tune(keys, n_problems=48, budget_ms=400.0, log=print):
             continue
         best = None
         for smp in SAMPLES:
-            sc, ns = score(probs, smp, 32, budget_ms)
-            log("[tune] %s samples %d lanes 32: score %.1f solved %d" % (key, smp, sc, ns))
+            sc, ns = score(probs, smp, LANES_FIRST, budget_ms)
+            log("[tune] %s samples %d bridge lanes %d: score %.1f solved %d" % (key, smp, LANES_FIRST, sc, ns))
             if best is None or sc < best[0]:
-                best = (sc, smp, 32)
+                best = (sc, smp, LANES_FIRST)
         for ln in LANES:
-            if ln == 32:
+            if ln == LANES_FIRST:
                 continue
             sc, ns = score(probs, best[1], ln, budget_ms)
-            log("[tune] %s samples %d lanes %d: score %.1f solved %d" % (key, best[1], ln, sc, ns))
+            log("[tune] %s samples %d bridge lanes %d: score %.1f solved %d" % (key, best[1], ln, sc, ns))
             if sc < best[0]:
                 best = (sc, best[1], ln)
-        table[key] = {"samples": best[1], "lanes_extension": best[2], "lanes_bridge": 64, "score": best[0]}
+        table[key] = {"samples": best[1], "lanes_extension": DEFAULT["lanes_extension"], "lanes_bridge": best[2],
+                      "score": best[0]}
     return table
 
 
