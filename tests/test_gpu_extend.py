@@ -58,6 +58,8 @@ PROBS = [
     # the start configuration is grazed by an obstacle at t ~ 0.43 s: most
     # forward edges pass within 1e-4 m of contact (exempt decisions)
     ("arm6-ir-grazing", lambda: _small(scenes.arm6(1), 1024, groups=8)),
+    # a batch that fills no launch shape evenly (ragged blocks and tiles)
+    ("arm6-ir-ragged", lambda: _small(scenes.arm6(2), 1000 + 7, groups=8)),
     # self-collision and fixed boxes switched on
     ("arm6-static-ir", lambda: _small(scenes.arm6static(8), 1024, groups=8)),
     ("arm7-static-rr", lambda: _small(scenes.with_static(scenes.arm7rr(30, n_obs=8)), 1024, groups=16)),
