@@ -349,6 +349,7 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
 // ---------------------------------------------------------------------------
 
 enum { kScanRho = 0, kScanConfig = 1, kScanBridge = 2 };
+constexpr int kMinSliceNodes = 32;  // nearest-node scans: nodes per slice at least
 
 
 // One block = one tile of up to 256 queries (one per thread) against the
@@ -399,9 +400,19 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     __syncthreads();
     const int np = s_np;
     const int64_t total = s_pre[np];
+    // nearest-node scans of small node sets use fewer slices (each of at least
+    // kMinSliceNodes nodes); the blocks past them leave (the keys they would
+    // merge into start empty).  Bridge scans keep every slice: their merge
+    // reads one partial result per slice.
+    int nch = a.nch;
+    if (MODE != kScanBridge) {
+        const int64_t want = (total + kMinSliceNodes - 1) / kMinSliceNodes;
+        nch = (int)min<int64_t>(nch, max<int64_t>(want, 1));
+        if ((int)blockIdx.y >= nch) return;
+    }
     const bool act = tid < n;
     const int q = act ? (a.order ? a.order[tile.y + tid] : tile.y + tid) : 0;
-    const int64_t c0 = (int64_t)blockIdx.y * total / a.nch, c1 = (int64_t)(blockIdx.y + 1) * total / a.nch;
+    const int64_t c0 = (int64_t)blockIdx.y * total / nch, c1 = (int64_t)(blockIdx.y + 1) * total / nch;
     float qx[kMaxDof];
     float aq = 0.f;
 #pragma unroll
