@@ -257,7 +257,7 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
         }
     }
     if (shared && O == 0) segt.assign(nseg + 1, INFINITY);
-    // LDS: segment table, spheres, pair table (padded to float4), times
+    // LDS: segment table, spheres, waypoint times (generic mode), goal centres, boxes
     sc.lds_sph = sc.O_pad * nseg * 2;
     sc.lds_t = sc.lds_sph + S;
     sc.lds_goal = sc.lds_t + (shared ? 0 : (int)((segt.size() + 3) / 4));

@@ -61,8 +61,8 @@ struct SceneDev {
     const float *seg_t;         // shared mode: [n_seg+1]; generic: [O_pad][n_seg+1]
 };
 
-// Stage the scene into LDS: obstacle segment table, robot spheres, pair table
-// and (generic mode) waypoint times.  Every thread of the block must call it.
+// Stage the scene into LDS: obstacle segment table, robot spheres, (generic
+// mode) waypoint times, the sphere centres at q_g and the fixed boxes.  Every thread of the block must call it.
 __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds) {
     const int n = sc.O_pad * sc.n_seg * 2;
     for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = sc.seg[i];
