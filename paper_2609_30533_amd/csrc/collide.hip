@@ -160,9 +160,7 @@ hipError_t launch_goal_centers(const SceneDev &sc, float4 *out) {
 // one wave.
 // ---------------------------------------------------------------------------
 
-constexpr int32_t kNoHit = 0x7fffffff;
 constexpr int kMaxItems = 16;   // work items per edge at most
-constexpr int kCntStride = 32;  // ints between rank counters (128 bytes)
 
 __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     const EdgeBufs &eb = a.eb;
@@ -623,6 +621,7 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
     const int64_t want = (E + per_block - 1) / per_block;
     a.nb_items = (int)std::min<int64_t>(std::max<int64_t>(want, min_item_blocks), 8192);
     a.flat = 0;
+    a.skip_finish = 0;
     return a;
 }
 
@@ -656,7 +655,7 @@ hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
         k_edge_items<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, decltype(split)::value>
             <<<dim3(a.nb_items), dim3(256), lds, s>>>(a);
     });
-    k_edge_finish<<<a.nb_edge, 256, 0, s>>>(a);
+    if (!a.skip_finish) k_edge_finish<<<a.nb_edge, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 

@@ -899,8 +899,20 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
     const Work &k = a.w;
     float bu = INFINITY, bc = INFINITY;
     int bw = -1;
+    unsigned long long states = 0, edges = 0;
     for (int64_t w = tid; w < a.B; w += blockDim.x) {
-        const bool ok = k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w] && k.br_free[w];
+        // finish step of the bridge edge checks: free / first hit and work
+        bool bfree = false;
+        const bool bv = k.br_valid[w];
+        if (bv) {
+            const int32_t h = a.eb.hit[w];
+            bfree = h == kNoHit;
+            k.br_free[w] = bfree ? 1 : 0;
+            // algorithmic work: the states up to the first hit, all n+1 when free
+            states += bfree ? (unsigned long long)a.eb.n[w] + 1ull : (unsigned long long)h + 1ull;
+            edges += 1;
+        }
+        const bool ok = k.status[w] == ST_STATUS_ADVANCED && bv && bfree;
         if (!ok) {
             k.Up[w] = INFINITY;
             k.Cp[w] = INFINITY;
@@ -910,6 +922,16 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
             bw = (int)w;
         }
     }
+    for (int o = 32; o > 0; o >>= 1) {
+        states += __shfl_down(states, o, 64);
+        edges += __shfl_down(edges, o, 64);
+    }
+    if ((tid & 63) == 0 && edges) {
+        atomicAdd(&a.work_br[0], edges);
+        atomicAdd(&a.work_br[1], states);
+    }
+    // the rank lists of the edge pipeline are consumed: empty for the next launch
+    if (tid < a.eb.mmax) a.eb.cnt[tid * kCntStride] = 0;
     sU[tid] = bu;
     sC[tid] = bc;
     sW[tid] = bw;
@@ -1307,6 +1329,7 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ba.w = w;
     a.edge_br = edge_args(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true),
                           p->d_plan->work + 2, min_item_blocks, split_for(p->split_br, launch_edges));
+    a.edge_br.skip_finish = 1;  // k_publish reads the bridge hits itself
     // publish (a7)
     PublishArgs &pb = a.publish;
     pb.pl = p->d_plan;
@@ -1315,6 +1338,8 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     pb.w = w;
     if (out) pb.out = *out;
     else memset(&pb.out, 0, sizeof pb.out);
+    pb.eb = p->ebufs;
+    pb.work_br = p->d_plan->work + 2;
     // allocation update (a8 / a9)
     RootsArgs &ra = a.roots;
     ra.sc = p->sc;
@@ -1411,7 +1436,6 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     ST_HIP(launch_edge_plan_multi(L.edge_br, L.P, L.nb_edge, s));
     for (const BatchClass &c : L.classes)
         ST_HIP(launch_edge_items_multi(c.key, c.split_br, L.edge_br, c.members, c.n, c.nb_items_br, c.lds, s));
-    ST_HIP(launch_edge_finish_multi(L.edge_br, L.P, L.nb_edge, s));
     k_publish<true><<<dim3(1, L.P), 1024, 0, s>>>(PublishArgs{}, L.publish, RootsArgs{}, L.roots);
     ST_HIP(hipGetLastError());
     return ST_OK;

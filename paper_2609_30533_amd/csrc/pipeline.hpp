@@ -88,6 +88,9 @@ struct PublishArgs {
     const int8_t *dir;
     Work w;
     st_extend_out out;
+    // bridge edge results still in the edge buffers (finish step done here)
+    EdgeBufs eb;
+    unsigned long long *work_br;  // two work counters
 };
 
 struct RootsArgs {

@@ -89,6 +89,11 @@ struct WindowsDev {
     const uint8_t *gfree;         // goal grid, [k_hi - k_lo + 1]
 };
 
+// Edge-check pipeline: hit[e] holds kNoHit until a colliding state is found;
+// the rank counters sit kCntStride ints (128 bytes) apart.
+constexpr int32_t kNoHit = 0x7fffffff;
+constexpr int kCntStride = 32;
+
 // Work buffers of the edge-check pipeline (capacity cap edges).
 struct EdgeBufs {
     int64_t cap = 0;
@@ -114,6 +119,7 @@ struct EdgeArgs {
     int32_t nb_edge;            // blocks of the per-edge kernels
     int32_t nb_items;           // blocks of the item kernel
     int32_t flat;               // > 0: short edges, flattened one-kernel path, this many per block
+    int32_t skip_finish;        // 1: the consumer of the results does the finish step itself
 };
 
 // Per-batch work buffers (capacity Bcap workers).
