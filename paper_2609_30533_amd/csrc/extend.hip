@@ -245,15 +245,14 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
     const int tid = threadIdx.x;
     const int nsets = a.mode == 0 ? a.n_pools : 2;
     for (int i = tid; i < nsets; i += blockDim.x) cnt[i] = 0;
+    // the snapshot every worker of this batch sees (one pool per thread: a
+    // serial copy would wait for every load in turn); loaded here, stored
+    // after the worker loads, since a load behind a store waits for it
+    int32_t snap_count = 0;
+    float snap_U = 0.f;
     if (a.mode == 0) {
-        // the snapshot every worker of this batch sees (one pool per thread:
-        // a serial copy would wait for every load in turn)
-        if (tid < a.n_pools) a.pl->count_snap[tid] = a.pl->count[tid];
-        if (tid == 0) {
-            const float U = a.pl->U;
-            a.pl->U_snap = U;
-            a.pl->improved = 0;
-        }
+        if (tid < a.n_pools) snap_count = a.pl->count[tid];
+        if (tid == 0) snap_U = a.pl->U;
     }
     __syncthreads();
     // R consecutive workers per thread and pass, all loads before the stores
@@ -265,18 +264,31 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
         int8_t dr[R];
         int32_t g[R];
         int8_t stt[R];
+        // unconditional loads (a worker past B reads worker B - 1 and is
+        // ignored): guarded loads would each wait before the next one issues
+        if (a.mode == 0) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t w = base + (int64_t)tid * R + r;
-            const bool in = w < a.B;
-            if (a.mode == 0) {
-                f[r] = in ? a.s.flags[w] : ST_FLAG_SKIP;
-                dr[r] = in ? a.s.dir[w] : 0;
-                g[r] = in ? a.s.grp[w] : -1;
-            } else {
-                stt[r] = in ? a.status[w] : 0;
-                dr[r] = in ? a.dir[w] : 0;
+            for (int r = 0; r < R; ++r) {
+                const int64_t w = base + (int64_t)tid * R + r;
+                const int64_t wc = w < a.B ? w : a.B - 1;
+                f[r] = a.s.flags[wc];
+                dr[r] = a.s.dir[wc];
+                g[r] = a.s.grp[wc];
             }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (base + (int64_t)tid * R + r >= a.B) f[r] = ST_FLAG_SKIP;
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int64_t w = base + (int64_t)tid * R + r;
+                const int64_t wc = w < a.B ? w : a.B - 1;
+                stt[r] = a.status[wc];
+                dr[r] = a.dir[wc];
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                if (base + (int64_t)tid * R + r >= a.B) stt[r] = 0;
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -303,6 +315,13 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
         // positions inside the sets (kept for the single-pass case)
 #pragma unroll
         for (int r = 0; r < R; ++r) pos[r] = wave_bucket_add(cnt, sets[r]);
+    }
+    if (a.mode == 0) {
+        if (tid < a.n_pools) a.pl->count_snap[tid] = snap_count;
+        if (tid == 0) {
+            a.pl->U_snap = snap_U;
+            a.pl->improved = 0;
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -514,75 +533,85 @@ __global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av
     const SceneDev &sc = a.sc;
     const int d = sc.d, W = d + 1;
     const Work &k = a.w;
-    k.new_idx[w] = -1;
-    k.parent[w] = -1;
-    k.edge_valid[w] = 0;
+    // every load is issued before the first store (a store ahead of a load
+    // would make the load's wait include the store's completion)
     const uint8_t f = a.s.flags[w];
     const int8_t dir = a.s.dir[w];
     const int32_t g = a.s.grp[w];
-    // a backward worker must name an existing group / slot
-    if ((f & ST_FLAG_SKIP) || (dir != 0 && (g < 0 || g >= a.tree.n_pools - 1))) {
-        k.status[w] = ST_STATUS_SKIPPED;
-        return;
-    }
-    k.status[w] = ST_STATUS_TRAPPED;
-    const float sigma = dir == 0 ? 1.f : -1.f;
+    const unsigned long long key = k.nn_key[w];
+    const float Tw = a.s.T[w];
     float xr[kMaxDof + 1], xn[kMaxDof + 1], xnew[kMaxDof + 1];
-    for (int j = 0; j < d; ++j) xr[j] = a.s.qr[(int64_t)j * a.B + w];
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j) xr[j] = j < d ? a.s.qr[(int64_t)j * a.B + w] : 0.f;
     xr[d] = a.s.tr[w];
+    // a backward worker must name an existing group / slot
+    const bool skip = (f & ST_FLAG_SKIP) || (dir != 0 && (g < 0 || g >= a.tree.n_pools - 1));
     const bool virt = a.variant == ST_INTERVAL_ROOT && dir == 1 && (f & ST_FLAG_USE_NEW);
+    int8_t status = skip ? ST_STATUS_SKIPPED : ST_STATUS_TRAPPED;
+    bool ok = !skip && (virt || key != kNoKey);  // TRAPPED when nothing is admissible
     int32_t idx = -1;
-    if (virt) {
+    float cost0 = 0.f, root0 = 0.f;
+    if (ok && virt) {
         for (int j = 0; j < d; ++j) xn[j] = sc.q_g[j];
-        xn[d] = a.s.T[w];
-    } else {
-        const unsigned long long key = k.nn_key[w];
-        if (key == kNoKey) return;  // TRAPPED: nothing admissible
+        xn[d] = Tw;
+        root0 = Tw;
+    } else if (ok) {
         idx = (int32_t)(key & 0xffffffffu);
         for (int j = 0; j <= d; ++j) xn[j] = a.tree.x[(int64_t)j * a.tree.total + idx];
+        cost0 = a.tree.cost[idx];
+        root0 = dir == 0 ? 0.f : a.tree.rootT[idx];
     }
-    float D2 = 0.f;
-    for (int j = 0; j < d; ++j) {
-        const float e = xr[j] - xn[j];
-        D2 = fmaf(e, e, D2);
-    }
-    float step;
-    if (a.variant == ST_INTERVAL_ROOT) {
-        const float vd = sigma * sc.v * (xr[d] - xn[d]);
-        const float w2 = vd * fabsf(vd);
-        if (!(D2 <= w2 && w2 > 0.f)) return;  // rho infinite
-        const float rho = sqrtf(0.5f * (D2 + w2));
-        const float alpha = fminf(1.f, a.eta / rho);  // Alg. 1: same fraction in q and t
-        for (int j = 0; j <= d; ++j) xnew[j] = fmaf(alpha, xr[j] - xn[j], xn[j]);
-        float s2 = 0.f;
+    float step = 0.f;
+    if (ok) {
+        const float sigma = dir == 0 ? 1.f : -1.f;
+        float D2 = 0.f;
         for (int j = 0; j < d; ++j) {
-            const float e = xnew[j] - xn[j];
-            s2 = fmaf(e, e, s2);
+            const float e = xr[j] - xn[j];
+            D2 = fmaf(e, e, D2);
         }
-        step = sqrtf(s2);
-    } else {
-        const float D = sqrtf(D2);
-        if (!(D > 0.f)) return;  // no proposal
-        const float fr = fminf(1.f, a.eta / D);
-        float s2 = 0.f;
-        for (int j = 0; j < d; ++j) {
-            xnew[j] = fmaf(fr, xr[j] - xn[j], xn[j]);
-            const float e = xnew[j] - xn[j];
-            s2 = fmaf(e, e, s2);
+        if (a.variant == ST_INTERVAL_ROOT) {
+            const float vd = sigma * sc.v * (xr[d] - xn[d]);
+            const float w2 = vd * fabsf(vd);
+            if (!(D2 <= w2 && w2 > 0.f)) {
+                ok = false;  // rho infinite
+            } else {
+                const float rho = sqrtf(0.5f * (D2 + w2));
+                const float alpha = fminf(1.f, a.eta / rho);  // Alg. 1: same fraction in q and t
+                for (int j = 0; j <= d; ++j) xnew[j] = fmaf(alpha, xr[j] - xn[j], xn[j]);
+                float s2 = 0.f;
+                for (int j = 0; j < d; ++j) {
+                    const float e = xnew[j] - xn[j];
+                    s2 = fmaf(e, e, s2);
+                }
+                step = sqrtf(s2);
+            }
+        } else {
+            const float D = sqrtf(D2);
+            if (!(D > 0.f)) {
+                ok = false;  // no proposal
+            } else {
+                const float fr = fminf(1.f, a.eta / D);
+                float s2 = 0.f;
+                for (int j = 0; j < d; ++j) {
+                    xnew[j] = fmaf(fr, xr[j] - xn[j], xn[j]);
+                    const float e = xnew[j] - xn[j];
+                    s2 = fmaf(e, e, s2);
+                }
+                step = sqrtf(s2);
+                xnew[d] = xn[d] + sigma * step / sc.v;  // Eq. 8: maximum-speed timing
+            }
         }
-        step = sqrtf(s2);
-        xnew[d] = xn[d] + sigma * step / sc.v;  // Eq. 8: maximum-speed timing
+        if (ok && !(xnew[d] >= 0.f && xnew[d] <= sc.H)) ok = false;  // leaves [0, H]
     }
-    if (!(xnew[d] >= 0.f && xnew[d] <= sc.H)) return;  // leaves [0, H]
-    // loads before the stores (which may alias them for the compiler)
-    const float cost0 = virt ? 0.f : a.tree.cost[idx];
-    const float root0 = dir == 0 ? 0.f : (virt ? a.s.T[w] : a.tree.rootT[idx]);
+    k.status[w] = status;
+    k.new_idx[w] = -1;
+    k.edge_valid[w] = ok ? 1 : 0;
+    k.parent[w] = ok ? idx : -1;
+    if (!ok) return;
     for (int j = 0; j <= d; ++j) {
         k.xn[w * W + j] = xn[j];
         k.xnew[w * W + j] = xnew[j];
     }
-    k.edge_valid[w] = 1;
-    k.parent[w] = idx;
     k.cost_new[w] = cost0 + step;
     k.rootT_new[w] = root0;
 }
@@ -618,26 +647,53 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
         uint8_t ev[R], ef[R];
         int8_t dr[R];
         int32_t gr[R];
+        // unconditional loads (a worker past B reads worker B - 1 and is
+        // ignored): guarded loads would each wait before the next one issues
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t w = c0 + (int64_t)tid * R + r;
             const bool in = w < a.B;
-            ev[r] = in ? k.edge_valid[w] : 0;
-            ef[r] = in ? k.edge_free[w] : 0;
-            dr[r] = in ? a.s.dir[w] : 0;
-            gr[r] = in ? a.s.grp[w] : 0;
-            par0[r] = in ? k.parent[w] : 0;
+            const int64_t wc = in ? w : a.B - 1;
+            const uint8_t v0 = k.edge_valid[wc], f0 = k.edge_free[wc];
+            const int8_t d0 = a.s.dir[wc];
+            const int32_t g0 = a.s.grp[wc], p0 = k.parent[wc];
+            ev[r] = in ? v0 : 0;
+            ef[r] = in ? f0 : 0;
+            dr[r] = in ? d0 : 0;
+            gr[r] = in ? g0 : 0;
+            par0[r] = in ? p0 : 0;
         }
         int tot = 0;
+        bool trapped[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             need[r] = 0;
+            trapped[r] = false;
             if (ev[r] && worker_pool(dr[r], gr[r]) == p) {
-                if (!ef[r]) k.status[c0 + (int64_t)tid * R + r] = ST_STATUS_TRAPPED;  // the extension collides
+                if (!ef[r]) trapped[r] = true;  // the extension collides
                 else need[r] = par0[r] < 0 ? 2 : 1;
             }
             tot += need[r];
         }
+        // the payload of this pool's new nodes, every load in flight together
+        // and ahead of the first store (a load behind a store waits for it)
+        // (no default values: a select on a guarded load would wait for it)
+        float xv[R][kMaxDof + 1], cn[R], rn[R], Tw[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t w = c0 + (int64_t)tid * R + r;
+            if (need[r] > 0) {
+#pragma unroll
+                for (int jj = 0; jj <= kMaxDof; ++jj)
+                    if (jj <= d) xv[r][jj] = k.xnew[w * W + jj];
+                cn[r] = k.cost_new[w];
+                rn[r] = k.rootT_new[w];
+                Tw[r] = a.s.T[w];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (trapped[r]) k.status[c0 + (int64_t)tid * R + r] = ST_STATUS_TRAPPED;
         // block-wide exclusive prefix of the threads' totals (worker order)
         int incl = tot;
 #pragma unroll
@@ -669,12 +725,7 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
                 int64_t idx = base + snap + off;
                 int32_t par = par0[r];
                 const bool virt = par < 0;
-                // all loads first: the tree stores may alias them for the compiler
-                float xv[kMaxDof + 1];
-#pragma unroll
-                for (int jj = 0; jj <= kMaxDof; ++jj) xv[jj] = jj <= d ? k.xnew[w * W + jj] : 0.f;
-                const float cn = k.cost_new[w], rn = k.rootT_new[w];
-                const float T = a.s.T[w];
+                const float T = Tw[r];
                 if (virt) {
                     // materialise the backward tree rooted at (q_g, T)
 #pragma unroll
@@ -691,10 +742,10 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
                 }
 #pragma unroll
                 for (int jj = 0; jj <= kMaxDof; ++jj)
-                    if (jj <= d) a.tree.x[(int64_t)jj * a.tree.total + idx] = xv[jj];
+                    if (jj <= d) a.tree.x[(int64_t)jj * a.tree.total + idx] = xv[r][jj];
                 a.tree.parent[idx] = par;
-                a.tree.cost[idx] = cn;
-                a.tree.rootT[idx] = rn;
+                a.tree.cost[idx] = cn[r];
+                a.tree.rootT[idx] = rn[r];
                 k.new_idx[w] = (int32_t)idx;
                 k.status[w] = ST_STATUS_ADVANCED;
                 atomicMax(&s_last, (int)(off + need[r]));
@@ -745,12 +796,15 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
         }
     }
     if (lane != 0) return;
-    k.bridge[w] = -1;
-    k.br_valid[w] = 0;
-    k.Up[w] = INFINITY;
-    k.Cp[w] = INFINITY;
-    if (!adv || bi == 0xffffffffu) return;
-    // all loads first: the stores may alias them for the compiler
+    if (!adv || bi == 0xffffffffu) {
+        k.bridge[w] = -1;
+        k.br_valid[w] = 0;
+        k.Up[w] = INFINITY;
+        k.Cp[w] = INFINITY;
+        return;
+    }
+    // all loads first: the stores may alias them for the compiler, and a load
+    // behind a store waits for the store's completion too
     float y[kMaxDof + 1], xn[kMaxDof + 1];
 #pragma unroll
     for (int j = 0; j <= kMaxDof; ++j) {
@@ -900,25 +954,25 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
     float bu = INFINITY, bc = INFINITY;
     int bw = -1;
     unsigned long long states = 0, edges = 0;
+    // No global store before the last load of this pass (a store ahead of a
+    // load makes the load's wait include the store's completion): the bridge
+    // finish step (free / first hit, work counters) and the incumbent
+    // candidates read the workers' records; the outputs are written below.
     for (int64_t w = tid; w < a.B; w += blockDim.x) {
-        // finish step of the bridge edge checks: free / first hit and work
-        bool bfree = false;
         const bool bv = k.br_valid[w];
+        const int8_t st = k.status[w];
+        const int32_t h = a.eb.hit[w];
+        const int32_t n = a.eb.n[w];
+        const float up = k.Up[w], cp = k.Cp[w];
+        const bool bfree = bv && h == kNoHit;
         if (bv) {
-            const int32_t h = a.eb.hit[w];
-            bfree = h == kNoHit;
-            k.br_free[w] = bfree ? 1 : 0;
             // algorithmic work: the states up to the first hit, all n+1 when free
-            states += bfree ? (unsigned long long)a.eb.n[w] + 1ull : (unsigned long long)h + 1ull;
+            states += bfree ? (unsigned long long)n + 1ull : (unsigned long long)h + 1ull;
             edges += 1;
         }
-        const bool ok = k.status[w] == ST_STATUS_ADVANCED && bv && bfree;
-        if (!ok) {
-            k.Up[w] = INFINITY;
-            k.Cp[w] = INFINITY;
-        } else if (lex_less(k.Up[w], k.Cp[w], (int)w, bu, bc, bw)) {
-            bu = k.Up[w];
-            bc = k.Cp[w];
+        if (st == ST_STATUS_ADVANCED && bfree && lex_less(up, cp, (int)w, bu, bc, bw)) {
+            bu = up;
+            bc = cp;
             bw = (int)w;
         }
     }
@@ -926,12 +980,6 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
         states += __shfl_down(states, o, 64);
         edges += __shfl_down(edges, o, 64);
     }
-    if ((tid & 63) == 0 && edges) {
-        atomicAdd(&a.work_br[0], edges);
-        atomicAdd(&a.work_br[1], states);
-    }
-    // the rank lists of the edge pipeline are consumed: empty for the next launch
-    if (tid < a.eb.mmax) a.eb.cnt[tid * kCntStride] = 0;
     sU[tid] = bu;
     sC[tid] = bc;
     sW[tid] = bw;
@@ -967,18 +1015,29 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
         }
         pl->iter = it + 1;
     }
-    // optional caller outputs
+    if ((tid & 63) == 0 && edges) {
+        atomicAdd(&a.work_br[0], edges);
+        atomicAdd(&a.work_br[1], states);
+    }
+    // the rank lists of the edge pipeline are consumed: empty for the next launch
+    if (tid < a.eb.mmax) a.eb.cnt[tid * kCntStride] = 0;
+    // optional caller outputs (a candidate that is not a free bridge of an
+    // advanced worker reports U = C = infinity)
     const st_extend_out &o = a.out;
-    const int W = 0;
-    (void)W;
-    for (int64_t w = tid; w < a.B; w += blockDim.x) {
-        if (o.status) o.status[w] = k.status[w];
-        if (o.parent) o.parent[w] = k.parent[w];
-        if (o.new_idx) o.new_idx[w] = k.new_idx[w];
-        if (o.bridge) o.bridge[w] = k.bridge[w];
-        if (o.bridge_ok) o.bridge_ok[w] = (k.status[w] == ST_STATUS_ADVANCED && k.br_valid[w]) ? k.br_free[w] : 0;
-        if (o.Up) o.Up[w] = k.Up[w];
-        if (o.Cp) o.Cp[w] = k.Cp[w];
+    if (o.status || o.parent || o.new_idx || o.bridge || o.bridge_ok || o.Up || o.Cp) {
+        for (int64_t w = tid; w < a.B; w += blockDim.x) {
+            const int8_t st = k.status[w];
+            const bool bv = k.br_valid[w];
+            const bool bfree = bv && a.eb.hit[w] == kNoHit;
+            const bool ok = st == ST_STATUS_ADVANCED && bfree;
+            if (o.status) o.status[w] = st;
+            if (o.parent) o.parent[w] = k.parent[w];
+            if (o.new_idx) o.new_idx[w] = k.new_idx[w];
+            if (o.bridge) o.bridge[w] = k.bridge[w];
+            if (o.bridge_ok) o.bridge_ok[w] = ok ? 1 : 0;
+            if (o.Up) o.Up[w] = ok ? k.Up[w] : INFINITY;
+            if (o.Cp) o.Cp[w] = ok ? k.Cp[w] : INFINITY;
+        }
     }
     // a8 / a9 in the same block (no launch of its own)
     __syncthreads();

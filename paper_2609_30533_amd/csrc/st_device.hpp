@@ -64,17 +64,32 @@ struct SceneDev {
 // Stage the scene into LDS: obstacle segment table, robot spheres, (generic
 // mode) waypoint times, the sphere centres at q_g and the fixed boxes.  Every thread of the block must call it.
 __device__ __forceinline__ void stage_obstacles(const SceneDev &sc, float4 *lds) {
+    const int t = threadIdx.x, bd = blockDim.x;
     const int n = sc.O_pad * sc.n_seg * 2;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) lds[i] = sc.seg[i];
-    for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_sph + i] = sc.sph[i];
-    if (sc.obs_mode == kObsGeneric) {
-        float *lt = reinterpret_cast<float *>(lds + sc.lds_t);
-        const int m = sc.O_pad * (sc.n_seg + 1);
-        for (int i = threadIdx.x; i < m; i += blockDim.x) lt[i] = sc.seg_t[i];
-    }
-    if (sc.goal)
-        for (int i = threadIdx.x; i < sc.S; i += blockDim.x) lds[sc.lds_goal + i] = sc.goal[i];
-    for (int i = threadIdx.x; i < 4 * sc.n_box; i += blockDim.x) lds[sc.lds_box + i] = sc.box[i];
+    const int m = sc.obs_mode == kObsGeneric ? sc.O_pad * (sc.n_seg + 1) : 0;
+    const int ng = sc.goal ? sc.S : 0, nb = 4 * sc.n_box;
+    float *lt = reinterpret_cast<float *>(lds + sc.lds_t);
+    // each thread's first element of every section: all the global loads are
+    // in flight together before the first LDS write (section after section,
+    // each write would wait for its own load in turn)
+    float4 v0, v1, v2, v3;
+    float v4;
+    if (t < n) v0 = sc.seg[t];
+    if (t < sc.S) v1 = sc.sph[t];
+    if (t < ng) v2 = sc.goal[t];
+    if (t < nb) v3 = sc.box[t];
+    if (t < m) v4 = sc.seg_t[t];
+    if (t < n) lds[t] = v0;
+    if (t < sc.S) lds[sc.lds_sph + t] = v1;
+    if (t < ng) lds[sc.lds_goal + t] = v2;
+    if (t < nb) lds[sc.lds_box + t] = v3;
+    if (t < m) lt[t] = v4;
+    // sections longer than the block
+    for (int i = t + bd; i < n; i += bd) lds[i] = sc.seg[i];
+    for (int i = t + bd; i < sc.S; i += bd) lds[sc.lds_sph + i] = sc.sph[i];
+    for (int i = t + bd; i < ng; i += bd) lds[sc.lds_goal + i] = sc.goal[i];
+    for (int i = t + bd; i < nb; i += bd) lds[sc.lds_box + i] = sc.box[i];
+    for (int i = t + bd; i < m; i += bd) lt[i] = sc.seg_t[i];
     __syncthreads();
 }
 
