@@ -228,10 +228,15 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     const EdgeBufs &eb = a.eb;
     const float *__restrict__ xa = a.xa;
     const float *__restrict__ xb = a.xb;
-    int32_t pre[17];
+    // prefix of the rank lists' lengths; the kMaxItems counters are read
+    // together (a loop up to mmax would wait for each load in turn)
+    int32_t cr[kMaxItems], pre[kMaxItems + 1];
+#pragma unroll
+    for (int r = 0; r < kMaxItems; ++r) cr[r] = eb.cnt[r * kCntStride];
     pre[0] = 0;
-    for (int r = 0; r < eb.mmax; ++r) pre[r + 1] = pre[r] + eb.cnt[r * kCntStride];
-    const int64_t total = pre[eb.mmax];
+#pragma unroll
+    for (int r = 0; r < kMaxItems; ++r) pre[r + 1] = pre[r] + (r < eb.mmax ? cr[r] : 0);
+    const int64_t total = pre[kMaxItems];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpe_shift = a.lpe_shift;
     const int lpe = 1 << lpe_shift;
