@@ -162,6 +162,47 @@ hipError_t launch_goal_centers(const SceneDev &sc, float4 *out) {
 
 constexpr int kMaxItems = 16;   // work items per edge at most
 
+// Both endpoint rows of edge e (rows of d + 1 floats: configuration, then
+// time), earlier time first.  All the row loads are issued before the first
+// use; a loop that consumed each element as it arrived would wait for every
+// load in turn.
+__device__ __forceinline__ void load_edge_rows(const float *xa, const float *xb, int64_t e, int d,
+                                               float (&A)[kMaxDof + 1], float (&B)[kMaxDof + 1]) {
+    const float *pa = xa + e * (d + 1), *pb = xb + e * (d + 1);
+#pragma unroll
+    for (int j = 0; j <= kMaxDof; ++j) {
+        A[j] = j <= d ? pa[j] : 0.f;
+        B[j] = j <= d ? pb[j] : 0.f;
+    }
+    if (A[d] > B[d]) {
+#pragma unroll
+        for (int j = 0; j <= kMaxDof; ++j) {
+            const float tmp = A[j];
+            A[j] = B[j];
+            B[j] = tmp;
+        }
+    }
+}
+
+// States of a discretised edge (Eq. 5 spacing): n = ceil(max(|dq|, v dt) / h),
+// at least 1; the count is taken in double precision.
+__device__ __forceinline__ int32_t edge_states(const float (&A)[kMaxDof + 1], const float (&B)[kMaxDof + 1], int d,
+                                               double v, double h) {
+    double D2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j) {
+        if (j < d) {
+            const double dq = (double)B[j] - (double)A[j];
+            D2 += dq * dq;
+        }
+    }
+    const double span = fmax(sqrt(D2), v * ((double)B[d] - (double)A[d]));
+    int64_t n = (int64_t)ceil(span / h);
+    if (n < 1) n = 1;
+    if (n > (1ll << 30)) n = 1ll << 30;
+    return (int32_t)n;
+}
+
 __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     const EdgeBufs &eb = a.eb;
     // states per chunk: lanes per chunk over lanes per state
@@ -169,26 +210,21 @@ __device__ __forceinline__ void edge_plan_body(const EdgeArgs &a, int bx) {
     const double v = a.sc.v_d, h = a.sc.h_d;
     const int64_t e = (int64_t)bx * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
-    const int w = d + 1;
     int m = 0;
-    if (e < a.E && !(a.valid && !a.valid[e])) {
-        const float *A = a.xa + e * w, *B = a.xb + e * w;
-        if (A[d] > B[d]) { const float *tmp = A; A = B; B = tmp; }
-        double D2 = 0.0;
-        for (int j = 0; j < d; ++j) {
-            const double dq = (double)B[j] - (double)A[j];
-            D2 += dq * dq;
+    if (e < a.E) {
+        // the flag and both rows in flight together
+        float A[kMaxDof + 1], B[kMaxDof + 1];
+        load_edge_rows(a.xa, a.xb, e, d, A, B);
+        const bool vld = !a.valid || a.valid[e];
+        if (vld) {
+            const int64_t n = edge_states(A, B, d, v, h);
+            const int64_t c = (n + L) / L;
+            m = (int)(c < mmax ? c : mmax);
+            eb.n[e] = (int32_t)n;
+            eb.hit[e] = kNoHit;
+        } else {
+            eb.n[e] = -1;
         }
-        const double span = fmax(sqrt(D2), v * ((double)B[d] - (double)A[d]));
-        int64_t n = (int64_t)ceil(span / h);
-        if (n < 1) n = 1;
-        if (n > (1ll << 30)) n = 1ll << 30;
-        const int64_t c = (n + L) / L;
-        m = (int)(c < mmax ? c : mmax);
-        eb.n[e] = (int32_t)n;
-        eb.hit[e] = kNoHit;
-    } else if (e < a.E) {
-        eb.n[e] = -1;
     }
     // rank lists: positions within the block from LDS counters (one per wave
     // and rank), then one global atomic per rank and block; every rank's
@@ -364,7 +400,7 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
     __shared__ float s_A[kFlatBlockEdges][kMaxDof + 1], s_B[kFlatBlockEdges][kMaxDof + 1];
     __shared__ int32_t s_off[kFlatBlockEdges + 1], s_n[kFlatBlockEdges], s_hit[kFlatBlockEdges];
     const SceneDev &sc = a.sc;
-    const int d = sc.d, W = d + 1;
+    const int d = sc.d;
     const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
     const int NE = a.flat * kFlatGroups;  // edges of this block
     const int64_t e0 = (int64_t)bx * NE;
@@ -372,22 +408,18 @@ __device__ __forceinline__ void edge_flat_body(const EdgeArgs &a, float4 *lds, i
     if (tid < kFlatBlockEdges) {
         const int64_t e = e0 + tid;
         int32_t n = -1;
-        if (tid < NE && e < a.E && !(a.valid && !a.valid[e])) {
-            const float *A = a.xa + e * W, *B = a.xb + e * W;
-            if (A[d] > B[d]) { const float *tmp = A; A = B; B = tmp; }
-            double D2 = 0.0;
-            for (int j = 0; j < d; ++j) {
-                const double dq = (double)B[j] - (double)A[j];
-                D2 += dq * dq;
-            }
-            const double span = fmax(sqrt(D2), sc.v_d * ((double)B[d] - (double)A[d]));
-            int64_t nn = (int64_t)ceil(span / sc.h_d);
-            if (nn < 1) nn = 1;
-            if (nn > (1ll << 30)) nn = 1ll << 30;
-            n = (int32_t)nn;
-            for (int j = 0; j <= kMaxDof; ++j) {
-                s_A[tid][j] = j <= d ? A[j] : 0.f;
-                s_B[tid][j] = j <= d ? B[j] : 0.f;
+        if (tid < NE && e < a.E) {
+            // the flag and both rows in flight together
+            float A[kMaxDof + 1], B[kMaxDof + 1];
+            load_edge_rows(a.xa, a.xb, e, d, A, B);
+            const bool vld = !a.valid || a.valid[e];
+            if (vld) {
+                n = edge_states(A, B, d, sc.v_d, sc.h_d);
+#pragma unroll
+                for (int j = 0; j <= kMaxDof; ++j) {
+                    s_A[tid][j] = A[j];
+                    s_B[tid][j] = B[j];
+                }
             }
         }
         s_n[tid] = n;
