@@ -378,7 +378,7 @@ constexpr int kMinSliceNodes = 32;  // nearest-node scans: nodes per slice at le
 // round is fetched into registers while the current one is scanned.
 template <int MODE, bool MULTI>
 __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av, const int32_t *members) {
-    __shared__ float sx[kTileQ][8];
+    __shared__ __align__(16) float sx[kTileQ][8];
     __shared__ float sT[kTileQ];
     __shared__ int32_t sI[kTileQ];
     __shared__ int32_t s_pool[kMaxPools + 1], s_pre[kMaxPools + 1], s_cnt[kMaxPools + 1];
@@ -454,9 +454,9 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
             while (k + 1 < np && v >= s_pre[k + 1]) ++k;
             const int p = s_pool[k];
             const int64_t gi = pool_base(a.tree, p) + (v - s_pre[k]);
+            // slots past d hold 0 (as the query's do): they add exact zeros
 #pragma unroll
-            for (int j = 0; j < kMaxDof; ++j)
-                if (j < d) rx[j] = X[(int64_t)j * total_cap + gi];
+            for (int j = 0; j < kMaxDof; ++j) rx[j] = j < d ? X[(int64_t)j * total_cap + gi] : 0.f;
             float tn = X[(int64_t)d * total_cap + gi];
             const bool filt = a.variant == ST_INTERVAL_ROOT && p > 0;
             rT = (filt || MODE == kScanBridge) ? a.tree.rootT[gi] : 0.f;
@@ -477,37 +477,44 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
         if (c + kTileQ < c1) fetch(c + kTileQ);
         const int m = (int)min<int64_t>(kTileQ, c1 - c);
         if (act) {
-            // unrolled so that the LDS reads of several nodes are in flight together
+            // a node is two 16-byte broadcast reads (all eight slots, the
+            // unused ones ignored); unrolled so that the reads of several
+            // nodes are in flight together.  The round's best node is kept
+            // as its LDS slot and its index read once after the round.
+            const float4 *sx4 = reinterpret_cast<const float4 *>(&sx[0][0]);
+            int kb = -1;
 #pragma unroll 8
             for (int k = 0; k < m; ++k) {
+                const float4 lo = sx4[2 * k], hi = sx4[2 * k + 1];
+                const float xs[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                // every slot: those past d are 0 on both sides and add exact zeros
                 float D2 = 0.f;
 #pragma unroll
                 for (int j = 0; j < kMaxDof; ++j) {
-                    if (j < d) {
-                        const float e = sx[k][j] - qx[j];
-                        D2 = fmaf(e, e, D2);
-                    }
+                    const float e = xs[j] - qx[j];
+                    D2 = fmaf(e, e, D2);
                 }
                 if (MODE == kScanConfig) {
-                    if (D2 < best) { best = D2; bi = sI[k]; }
+                    if (D2 < best) { best = D2; kb = k; }
                 } else {
                     // Eq. 7: admissible iff sigma (t_q - t) > 0 and D <= v sigma (t_q - t)
-                    const float vd = aq - sx[k][7];
+                    const float vd = aq - xs[7];
                     const float w2 = vd * fabsf(vd);
                     const bool adm = (D2 <= w2) && (w2 > 0.f);
                     const float key = D2 + w2;
                     if (MODE == kScanRho) {
-                        if (adm && key < best) { best = key; bi = sI[k]; }
+                        if (adm && key < best) { best = key; kb = k; }
                     } else {
                         const float arr = set < 0 ? sT[k] : 0.f;
                         if (adm && (arr < bestT || (arr == bestT && key < best))) {
                             bestT = arr;
                             best = key;
-                            bi = sI[k];
+                            kb = k;
                         }
                     }
                 }
             }
+            if (kb >= 0) bi = sI[kb];
         }
     }
     if (!act) return;
