@@ -264,15 +264,22 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     const EdgeBufs &eb = a.eb;
     const float *__restrict__ xa = a.xa;
     const float *__restrict__ xb = a.xb;
-    // prefix of the rank lists' lengths; the kMaxItems counters are read
-    // together (a loop up to mmax would wait for each load in turn)
-    int32_t cr[kMaxItems], pre[kMaxItems + 1];
+    // prefix of the rank lists' lengths: the kMaxItems counters are read
+    // together (a loop up to mmax would wait for each load in turn); the
+    // prefix goes to LDS (written here, visible after the staging barrier),
+    // where a lane's lookup by its own rank is a plain LDS read
+    __shared__ int32_t s_pre[kMaxItems + 1];
+    int32_t cr[kMaxItems];
 #pragma unroll
     for (int r = 0; r < kMaxItems; ++r) cr[r] = eb.cnt[r * kCntStride];
-    pre[0] = 0;
+    int32_t total32 = 0, mine = 0;
 #pragma unroll
-    for (int r = 0; r < kMaxItems; ++r) pre[r + 1] = pre[r] + (r < eb.mmax ? cr[r] : 0);
-    const int64_t total = pre[kMaxItems];
+    for (int r = 0; r < kMaxItems; ++r) {
+        if ((int)threadIdx.x == r) mine = total32;
+        total32 += r < eb.mmax ? cr[r] : 0;
+    }
+    if (threadIdx.x == kMaxItems) mine = total32;
+    const int64_t total = total32;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lpe_shift = a.lpe_shift;
     const int lpe = 1 << lpe_shift;
@@ -280,6 +287,7 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
     // a block without any item leaves before staging the scene (the grid is
     // sized for the largest launch; the item count is known only here)
     if ((int64_t)bx * (blockDim.x >> 6) * G >= total) return;
+    if (threadIdx.x <= kMaxItems) s_pre[threadIdx.x] = mine;
     stage_obstacles(sc, lds);
     const int sub = lane & (lpe - 1), gsel = lane >> lpe_shift;
     // SPLIT lanes per state: states per chunk ls, the lane's state slot and part
@@ -295,8 +303,8 @@ __device__ __forceinline__ void edge_items_body(const EdgeArgs &a, float4 *lds, 
         int e = 0, rank = 0;
         if (!done) {
             int r = 0;
-            while (v >= pre[r + 1]) ++r;
-            const int2 it = eb.items[(int64_t)r * eb.cap + (v - pre[r])];
+            while (v >= s_pre[r + 1]) ++r;
+            const int2 it = eb.items[(int64_t)r * eb.cap + (v - s_pre[r])];
             e = it.x;
             rank = it.y;
         }

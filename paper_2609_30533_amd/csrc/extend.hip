@@ -368,7 +368,7 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
 // ---------------------------------------------------------------------------
 
 enum { kScanRho = 0, kScanConfig = 1, kScanBridge = 2 };
-constexpr int kMinSliceNodes = 32;  // nearest-node scans: nodes per slice at least
+constexpr int kMinSliceNodes = 64;  // nearest-node scans: nodes per slice at least
 
 
 // One block = one tile of up to 256 queries (one per thread) against the
