@@ -421,9 +421,23 @@ __device__ __forceinline__ bool state_hits(const SceneDev &sc, const float4 *lds
                     if (l > 0 && alive) dh_compose(sc, l - 1, q[l - 1], f);
                     const int s0 = sc.link_first[l], s1 = sc.link_first[l + 1];
                     if (s1 > s0 && __ballot(alive) != 0) {
+                        // broad phase for links of three spheres or more: the
+                        // link's bounding sphere (its spheres' radii included)
+                        // clearing every obstacle of the tile by kBroadMargin
+                        // clears each of its spheres (the margin is far above
+                        // the FP32 error), so the pair tests decide the same;
+                        // the wave skips the link when all its lanes clear it
+                        bool need = alive;
+                        if (alive && s1 - s0 >= 3) {
+                            const float4 bl = sc.lbs[l];
+                            float bx, by, bz, bs;
+                            sphere_world(f, make_float4(bl.x, bl.y, bl.z, 0.0f), bx, by, bz, bs);
+                            need = sphere_clear<OT, UNI>(sc, bx, by, bz, bs, bl.w + kBroadMargin, nx, ny, nz, A, ro) <
+                                   0.0f;
+                        }
                         // this lane's spheres of the link: s = part (mod SPLIT)
                         float dmin = INFINITY;
-                        if (alive) {
+                        if (__ballot(need) != 0 && need) {
                             // two spheres per step: both offset reads are in flight together
                             const int first = s0 + ((part - s0) & (SPLIT - 1));
                             int s = first;
