@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # from the FETCH_SIZE / WRITE_SIZE profiles of the current kernels, scaled by a
 # plain copy kernel of known size (profiles/traffic_arm6_single.md); to be
 # measured again whenever the edge-check kernels change.
-EDGE_LAUNCH_HBM_BYTES = 1.595e6
+EDGE_LAUNCH_HBM_BYTES = 1.681e6
 
 
 def flops_per_state(prob) -> int:
