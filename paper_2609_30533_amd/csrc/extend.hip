@@ -698,9 +698,7 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
                 Tw[r] = a.s.T[w];
             }
         }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (trapped[r]) k.status[c0 + (int64_t)tid * R + r] = ST_STATUS_TRAPPED;
+
         // block-wide exclusive prefix of the threads' totals (worker order)
         int incl = tot;
 #pragma unroll
@@ -759,6 +757,11 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
             }
             off += need[r];
         }
+        // collided extensions (disjoint from the inserted workers), written
+        // last so that no load of this pass waits behind them
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (trapped[r]) k.status[c0 + (int64_t)tid * R + r] = ST_STATUS_TRAPPED;
         running += s_total;
         __syncthreads();
     }
