@@ -136,6 +136,9 @@ def _declare(L):
     L.orc_planner_export.argtypes = [C.c_void_p, f64, i32, f64, f64]
     L.orc_planner_import.argtypes = [C.c_void_p, i64, f64, i32, f64, f64, C.c_double, C.c_double, C.c_int64,
                                      C.c_int64, C.c_int64, _opt(f64), _opt(i32), _opt(u32), _opt(i64)]
+    L.orc_planner_bridge.argtypes = [C.c_void_p, C.c_int, f64, C.c_double, C.POINTER(C.c_double),
+                                     C.POINTER(C.c_uint8)]
+    L.orc_planner_bridge.restype = C.c_int64
     L.orc_planner_set_proposal.argtypes = [C.c_void_p, _opt(f64), C.c_double]
     L.orc_validate_path.argtypes = [S, C.c_int64, f64, C.c_double, C.c_double, C.c_double, C.c_char_p, C.c_int]
     L.orc_validate_path.restype = C.c_int
@@ -381,6 +384,15 @@ class Planner:
         o["xnew"] = o["xnew"].reshape(d + 1, B)
         o["improved"] = r
         return o
+
+    def bridge(self, sigma, x, x_rootT):
+        """Best-ranked bridge from x into the opposite set of the current trees:
+        (global index or -1, arrival time, fragile flag)."""
+        arr = C.c_double()
+        amb = C.c_uint8()
+        b = self.lib.orc_planner_bridge(self.h, int(sigma), np.ascontiguousarray(x, dtype=np.float64),
+                                        float(x_rootT), C.byref(arr), C.byref(amb))
+        return int(b), arr.value, bool(amb.value)
 
     def set_proposal(self, z, mix):
         self.lib.orc_planner_set_proposal(self.h, None if z is None else np.ascontiguousarray(z, dtype=np.float64),

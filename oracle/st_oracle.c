@@ -999,6 +999,15 @@ static int64_t best_bridge(const orc_planner *p, const int64_t *cnt, double U, i
     return best;
 }
 
+/* The best-ranked bridge from state x (direction sigma, root time x_rootT of
+ * x's own tree) into the opposite set of the planner's current trees, as the
+ * extend step selects it (test access to the ranking).  Returns the global
+ * index or -1; arr receives the candidate's arrival time. */
+int64_t orc_planner_bridge(const orc_planner *p, int sigma, const double *x, double x_rootT, double *arr,
+                           uint8_t *amb) {
+    return best_bridge(p, p->count, p->U, sigma, x, x_rootT, arr, amb);
+}
+
 int orc_planner_extend(orc_planner *p, int64_t B, const int8_t *dir, const uint8_t *flags, const int32_t *grp,
                        const double *T, const double *qr, const double *tr,
                        /* outputs (any may be NULL) */
@@ -1110,7 +1119,14 @@ int orc_planner_extend(orc_planner *p, int64_t B, const int8_t *dir, const uint8
             }
         }
     }
-    /* commit in worker order */
+    /* commit in worker order.  Reading of capacity (the paper does not
+     * bound the trees): the workers of a pool claim consecutive slots in
+     * worker order, a dropped worker's claim included, as an atomic slot
+     * counter would hand them out; a worker whose claim ends past the pool's
+     * capacity is dropped, so once one worker is dropped every later worker
+     * of that pool is dropped too (a suffix in worker order). */
+    int64_t claimed[1 + 256];
+    memcpy(claimed, p->count, sizeof(int64_t) * (size_t)p->n_pools);
     int64_t best_w = -1;
     for (int64_t i = 0; i < B; ++i) {
         orc_work *k = &wk[i];
@@ -1118,7 +1134,8 @@ int orc_planner_extend(orc_planner *p, int64_t B, const int8_t *dir, const uint8
         if (k->status == ORC_ST_ADVANCED) {
             int pool = k->pool;
             int need = k->parent < 0 ? 2 : 1;
-            if (p->count[pool] + need > p->cap[pool]) {
+            claimed[pool] += need;
+            if (claimed[pool] > p->cap[pool]) {
                 k->status = ORC_ST_DROPPED;
                 p->overflow = 1;
             } else {
