@@ -45,7 +45,7 @@ extern "C" {
 #define ST_EINVAL (-1)     /* bad sizes, NaN, t_min > t_max, v_max <= 0, ... */
 #define ST_ENOMEM (-2)
 #define ST_EHIP (-3)       /* a HIP runtime call failed */
-#define ST_ECAPACITY (-4)
+#define ST_ECAPACITY (-4)  /* no solution, and some insert was dropped because its tree pool was full */
 
 /* robot kinds */
 #define ST_ROBOT_TRANSLATE 0 /* sphere centre = (q0, q1[, q2]) + local offset (d = 2 or 3) */
@@ -73,7 +73,7 @@ extern "C" {
 #define ST_STATUS_SKIPPED 0
 #define ST_STATUS_TRAPPED 1  /* Alg. 1 returned TRAPPED */
 #define ST_STATUS_ADVANCED 2 /* x_new appended */
-#define ST_STATUS_DROPPED 3  /* advanced but the tree pool was full */
+#define ST_STATUS_DROPPED 3  /* advanced but the tree pool was full (see st_extend_batch) */
 
 /* Planner parameters.  The paper fixes N = 64, 1024 configurations per batch,
  * p_new = 0.05, p_guided = 0.95 and dt = 0.02 s (Sec. VI); eta, the edge
@@ -268,7 +268,13 @@ int st_sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples *ou
  * alpha = min(1, eta / rho); recycling: Eq. 8), the [0, H] and edge checks, the
  * insert (nodes of one pool are numbered in worker order; a virtual source is
  * materialised as a new tree root first), the best-ranked bridge into the
- * opposite set and its check, the candidate (U', C').  Then the incumbent takes
+ * opposite set and its check, the candidate (U', C').  Capacity: the advanced
+ * workers of a pool claim consecutive slots in worker order (two when a
+ * virtual root is materialised), dropped claims included, as an atomic slot
+ * counter hands them out; a worker whose claim ends past the pool's capacity
+ * gets ST_STATUS_DROPPED (so the dropped workers of a pool are a suffix in
+ * worker order), inserts nothing and takes no part in the incumbent update;
+ * st_info.overflow is set.  Then the incumbent takes
  * the lexicographic minimum (U', C', worker) if it improves on (U, C), and on a
  * strict drop of U the allocation is updated (interval root: repartition and
  * deactivation of trees rooted at T >= U; recycling: deactivation and donor
@@ -282,7 +288,10 @@ int st_iterate(st_problem *p, int64_t iters, void *stream);
 
 /* Full planning loop (Alg. 2 / Alg. 3) within the budget; out receives the
  * incumbent path (host, library-allocated).  Returns ST_OK, ST_NO_SOLUTION or
- * ST_TRIVIAL.  Synchronous. */
+ * ST_TRIVIAL; ST_ECAPACITY when the call ends without an incumbent and some
+ * insert was dropped for capacity (the trees stopped growing; out holds no
+ * states, its other fields are filled).  A path found despite dropped
+ * inserts is ST_OK with st_info.overflow set.  Synchronous. */
 int st_plan(st_problem *p, const st_budget *budget, st_path *out);
 
 void st_path_free(st_path *path);
@@ -301,7 +310,8 @@ int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals
                      st_path *out);
 
 /* The current incumbent path of a problem (host, library-allocated; free with
- * st_path_free).  Returns ST_OK or ST_NO_SOLUTION.  Synchronous. */
+ * st_path_free).  Returns ST_OK, ST_NO_SOLUTION, or ST_ECAPACITY as st_plan
+ * does.  Synchronous. */
 int st_path_get(st_problem *p, st_path *out);
 
 /* ---- many problems per launch (an addition to the paper's method) --------- */

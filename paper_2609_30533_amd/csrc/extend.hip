@@ -1134,27 +1134,35 @@ __global__ void k_fill_tiles(int64_t M, int set, int sigma, int4 *tiles, int32_t
 // path extraction and timestamps
 // ---------------------------------------------------------------------------
 
-__global__ void k_path(TreeDev tree, const PlanDev *pl, int32_t max_n, float *out, int32_t *n_out) {
+// Lengths of the incumbent's forward chain (v_f back to the root) and
+// backward chain (w_b to its root).  A chain only points to earlier nodes of
+// its own pool, so it cannot be longer than that pool's node count; a longer
+// walk means a corrupted tree and is reported as -1.
+__global__ void k_path_len(TreeDev tree, const PlanDev *pl, int32_t *len_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t f = pl->inc_f, b = pl->inc_b;
+    len_out[0] = len_out[1] = 0;
+    if (f < 0 || b < 0) return;
+    const int32_t heads[2] = {f, b};
+    for (int c = 0; c < 2; ++c) {
+        const int64_t limit = tree.total;
+        int64_t n = 0;
+        for (int32_t i = heads[c]; i >= 0 && n <= limit; i = tree.parent[i]) ++n;
+        len_out[c] = n > limit ? -1 : (int32_t)n;
+    }
+}
+
+// The incumbent path into out[(nf + nb)][d+1]: the forward chain written back
+// to front (root first), then the backward chain from w_b to its root.
+__global__ void k_path_copy(TreeDev tree, const PlanDev *pl, int32_t nf, int32_t nb, float *out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const int d = tree.d, W = d + 1;
-    if (pl->inc_f < 0 || pl->inc_b < 0) {
-        *n_out = 0;
-        return;
-    }
-    // chains only point to earlier nodes of the same pool; the cap guards
-    // against a corrupted snapshot
-    int nf = 0;
-    for (int32_t i = pl->inc_f; i >= 0 && nf <= max_n; i = tree.parent[i]) ++nf;
-    int n = 0;
-    if (nf <= max_n) {
-        int j = nf - 1;
-        for (int32_t i = pl->inc_f; i >= 0; i = tree.parent[i], --j)
-            for (int c = 0; c <= d; ++c) out[j * W + c] = tree.x[(int64_t)c * tree.total + i];
-        n = nf;
-        for (int32_t i = pl->inc_b; i >= 0 && n < max_n; i = tree.parent[i], ++n)
-            for (int c = 0; c <= d; ++c) out[n * W + c] = tree.x[(int64_t)c * tree.total + i];
-    }
-    *n_out = n;
+    int32_t i = pl->inc_f;
+    for (int j = nf - 1; j >= 0 && i >= 0; --j, i = tree.parent[i])
+        for (int c = 0; c <= d; ++c) out[(int64_t)j * W + c] = tree.x[(int64_t)c * tree.total + i];
+    i = pl->inc_b;
+    for (int j = nf; j < nf + nb && i >= 0; ++j, i = tree.parent[i])
+        for (int c = 0; c <= d; ++c) out[(int64_t)j * W + c] = tree.x[(int64_t)c * tree.total + i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1666,43 +1674,72 @@ int start_check(st_problem *p, bool *start_free, bool *trivial) {
 }
 
 // The incumbent path (forward chain, then backward chain) into host memory.
+// The chain lengths are read first, so the copy is sized exactly.
 int fetch_path(st_problem *p, hipStream_t s, st_path *out) {
     const int W = p->d + 1;
-    const int32_t max_n = 1 << 16;
+    int32_t *dlen = nullptr;
     float *dpath = nullptr;
-    int32_t *dn = nullptr;
-    int rc = ST_OK;
     PlanDev host;
-    if (hipMalloc((void **)&dpath, (size_t)max_n * W * sizeof(float)) != hipSuccess ||
-        hipMalloc((void **)&dn, sizeof(int32_t)) != hipSuccess) {
+    int32_t len[2] = {0, 0};
+    int rc = ST_OK;
+    if (hipMalloc((void **)&dlen, 2 * sizeof(int32_t)) != hipSuccess) {
         set_error("path extraction: out of device memory");
-        rc = ST_ENOMEM;
-    } else {
-        k_path<<<1, 1, 0, s>>>(p->tree, p->d_plan, max_n, dpath, dn);
-        int32_t n = 0;
-        if (hipMemcpyAsync(&n, dn, sizeof n, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipMemcpyAsync(&host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-            set_error("path extraction: device copy failed");
-            rc = ST_EHIP;
+        return ST_ENOMEM;
+    }
+    k_path_len<<<1, 1, 0, s>>>(p->tree, p->d_plan, dlen);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(len, dlen, sizeof len, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error("path extraction: device copy failed");
+        rc = ST_EHIP;
+    } else if (len[0] < 0 || len[1] < 0) {
+        set_error("path extraction: a parent chain does not end at a root");
+        rc = ST_EHIP;
+    }
+    const int64_t n = (int64_t)len[0] + len[1];
+    if (rc == ST_OK && n > 0) {
+        if (hipMalloc((void **)&dpath, (size_t)n * W * sizeof(float)) != hipSuccess) {
+            set_error("path extraction: out of device memory");
+            rc = ST_ENOMEM;
         } else {
-            std::vector<float> buf((size_t)std::max(n, 1) * W);
-            if (n > 0) (void)hipMemcpy(buf.data(), dpath, (size_t)n * W * sizeof(float), hipMemcpyDeviceToHost);
-            out->dof = p->d;
-            out->iterations = p->iter;
-            out->arrival = host.U;
-            out->length = host.C;
-            if (host.first_iter >= 0) out->first_solution_iter = host.first_iter;
-            if (n > 0) {
+            std::vector<float> buf((size_t)n * W);
+            k_path_copy<<<1, 1, 0, s>>>(p->tree, p->d_plan, len[0], len[1], dpath);
+            if (hipGetLastError() != hipSuccess ||
+                hipMemcpyAsync(buf.data(), dpath, buf.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess) {
+                set_error("path extraction: device copy failed");
+                rc = ST_EHIP;
+            } else {
                 out->n_states = n;
-                out->states = (double *)malloc(sizeof(double) * (size_t)n * W);
-                for (size_t i = 0; i < (size_t)n * W; ++i) out->states[i] = buf[i];
+                out->states = (double *)malloc(sizeof(double) * buf.size());
+                if (!out->states) {
+                    set_error("path extraction: out of host memory");
+                    rc = ST_ENOMEM;
+                    out->n_states = 0;
+                } else {
+                    for (size_t i = 0; i < buf.size(); ++i) out->states[i] = buf[i];
+                }
             }
-            rc = n > 0 ? ST_OK : ST_NO_SOLUTION;
+        }
+    }
+    if (rc == ST_OK) {
+        out->dof = p->d;
+        out->iterations = p->iter;
+        out->arrival = host.U;
+        out->length = host.C;
+        if (host.first_iter >= 0) out->first_solution_iter = host.first_iter;
+        if (n == 0) {
+            rc = ST_NO_SOLUTION;
+            // growth stopped by full pools is reported as a capacity error
+            if (host.overflow) {
+                set_error("no solution and the tree capacity is exhausted (inserts were dropped)");
+                rc = ST_ECAPACITY;
+            }
         }
     }
     if (dpath) (void)hipFree(dpath);
-    if (dn) (void)hipFree(dn);
+    (void)hipFree(dlen);
     return rc;
 }
 

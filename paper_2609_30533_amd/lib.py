@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_build", "libstprrtc.so")
 
 ST_OK, ST_NO_SOLUTION, ST_TRIVIAL = 0, 1, 2
+ST_ECAPACITY = -4
 SET_FORWARD, SET_ALL_BACKWARD = -1, -2
 METRIC_RHO, METRIC_CONFIG = 0, 1
 FLAG_SKIP, FLAG_USE_NEW = 1, 2
@@ -166,8 +167,8 @@ def load():
     return L
 
 
-def _check(rc, what):
-    if rc < 0:
+def _check(rc, what, allow=()):
+    if rc < 0 and rc not in allow:
         raise StError("%s failed (%d): %s" % (what, rc, load().st_last_error().decode()))
     return rc
 
@@ -353,13 +354,15 @@ class Problem:
     def plan(self, max_iters=0, max_ms=0.0, stop_at_first=False, iters_per_sync=0):
         b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
         path = Path()
-        rc = _check(self.L.st_plan(self.h, C.byref(b), C.byref(path)), "st_plan")
+        # a plan that ends without a path after dropping inserts for capacity
+        # is a result (rc = ST_ECAPACITY, no states), not an exception
+        rc = _check(self.L.st_plan(self.h, C.byref(b), C.byref(path)), "st_plan", allow=(ST_ECAPACITY,))
         return self._path_dict(rc, path)
 
     def path(self):
         """The current incumbent path (st_path_get)."""
         path = Path()
-        rc = _check(self.L.st_path_get(self.h, C.byref(path)), "st_path_get")
+        rc = _check(self.L.st_path_get(self.h, C.byref(path)), "st_path_get", allow=(ST_ECAPACITY,))
         return self._path_dict(rc, path)
 
     def _path_dict(self, rc, path):

@@ -231,8 +231,15 @@ def sphere_obstacles(rng, n_obs, n_wp, horizon, radii):
 # Workloads
 # ----------------------------------------------------------------------------
 
+def _pair_rng(rng, kind: int, seed: int, attempt: int):
+    """Random stream of the start/goal draw: attempt 0 continues the
+    problem's own stream (after the obstacles), attempt k > 0 is a separate
+    stream, so a problem can be redrawn keeping its obstacles."""
+    return rng if attempt == 0 else np.random.default_rng([0x5EED, kind, seed, 0x57A6, attempt])
+
+
 def disc2d(seed: int, n_obs: int = 8, horizon: float = 10.0, t_min: float = 2.0,
-           params: Params | None = None) -> Problem:
+           params: Params | None = None, attempt: int = 0) -> Problem:
     rng = np.random.default_rng([0x5EED, 1, seed])
     r_robot = 0.05
     wp = np.zeros((n_obs, 2, 4))
@@ -243,9 +250,10 @@ def disc2d(seed: int, n_obs: int = 8, horizon: float = 10.0, t_min: float = 2.0,
         v = speed * np.array([math.cos(heading), math.sin(heading)])
         wp[o, 0] = [0.0, c0[0], c0[1], 0.0]
         wp[o, 1] = [horizon, c0[0] + v[0] * horizon, c0[1] + v[1] * horizon, 0.0]
+    prng = _pair_rng(rng, 1, seed, attempt)
     while True:
-        qs = rng.uniform(r_robot, 1.0 - r_robot, size=2)
-        qg = rng.uniform(r_robot, 1.0 - r_robot, size=2)
+        qs = prng.uniform(r_robot, 1.0 - r_robot, size=2)
+        qg = prng.uniform(r_robot, 1.0 - r_robot, size=2)
         if np.linalg.norm(qs - qg) >= 0.5:
             break
     p = params or Params(variant=VARIANT_IR, n_groups=4, batch=256, eta=0.1, h=0.01,
@@ -260,12 +268,13 @@ def disc2d(seed: int, n_obs: int = 8, horizon: float = 10.0, t_min: float = 2.0,
 
 
 def arm6(seed: int, n_obs: int = 16, n_wp: int = 8, horizon: float = 20.0, t_min: float = 2.0,
-         params: Params | None = None) -> Problem:
+         params: Params | None = None, attempt: int = 0) -> Problem:
     rng = np.random.default_rng([0x5EED, 2, seed])
     links, sph = arm_spheres(UR5E_DH, 40, 0.08, 0.03)
     n_wp_arr, wp, r = sphere_obstacles(rng, n_obs, n_wp, horizon, np.full(n_obs, 0.1))
-    qs = rng.uniform(-math.pi, math.pi, size=6)
-    qg = rng.uniform(-math.pi, math.pi, size=6)
+    prng = _pair_rng(rng, 2, seed, attempt)
+    qs = prng.uniform(-math.pi, math.pi, size=6)
+    qg = prng.uniform(-math.pi, math.pi, size=6)
     p = params or Params(variant=VARIANT_IR, n_groups=8, batch=4096, eta=0.5, h=0.02,
                          cap_fwd=1 << 18, cap_bwd=1 << 16, seed=1)
     return Problem(
@@ -276,13 +285,14 @@ def arm6(seed: int, n_obs: int = 16, n_wp: int = 8, horizon: float = 20.0, t_min
 
 
 def arm7rr(seed: int, n_obs: int = 32, n_wp: int = 16, horizon: float = 60.0, t_min: float = 1.0,
-           params: Params | None = None) -> Problem:
+           params: Params | None = None, attempt: int = 0) -> Problem:
     rng = np.random.default_rng([0x5EED, 3, seed])
     links, sph = arm_spheres(ARM7_DH, 60, 0.08, 0.03)
     radii = rng.uniform(0.05, 0.15, size=n_obs)
     n_wp_arr, wp, r = sphere_obstacles(rng, n_obs, n_wp, horizon, radii)
-    qs = rng.uniform(-math.pi, math.pi, size=7)
-    qg = rng.uniform(-math.pi, math.pi, size=7)
+    prng = _pair_rng(rng, 3, seed, attempt)
+    qs = prng.uniform(-math.pi, math.pi, size=7)
+    qg = prng.uniform(-math.pi, math.pi, size=7)
     p = params or Params(variant=VARIANT_RR, n_groups=64, batch=8192, eta=0.5, h=0.02,
                          cap_fwd=1 << 18, cap_bwd=1 << 14, seed=1)
     return Problem(
@@ -292,7 +302,7 @@ def arm7rr(seed: int, n_obs: int = 32, n_wp: int = 16, horizon: float = 60.0, t_
         n_wp=n_wp_arr, wp=wp, obs_r=r, params=p, seed=seed)
 
 
-def mixed(seed: int) -> Problem:
+def mixed(seed: int, attempt: int = 0) -> Problem:
     """One problem of the heterogeneous batch (DOF 2/6/7, 4-64 obstacles)."""
     rng = np.random.default_rng([0x5EED, 4, seed])
     d = int(rng.choice([2, 6, 7]))
@@ -304,14 +314,14 @@ def mixed(seed: int) -> Problem:
     if d == 2:
         p = Params(variant=VARIANT_IR, n_groups=4, batch=64, eta=0.1, h=0.01,
                    cap_fwd=1 << cap_log, cap_bwd=1 << max(cap_log - 2, 10), seed=1)
-        return disc2d(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p)
+        return disc2d(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p, attempt=attempt)
     if d == 6:
         p = Params(variant=VARIANT_IR, n_groups=8, batch=64, eta=0.5, h=0.02,
                    cap_fwd=1 << cap_log, cap_bwd=1 << max(cap_log - 3, 10), seed=1)
-        return arm6(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p)
+        return arm6(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p, attempt=attempt)
     p = Params(variant=VARIANT_RR, n_groups=16, batch=64, eta=0.5, h=0.02,
                cap_fwd=1 << cap_log, cap_bwd=1 << max(cap_log - 4, 10), seed=1)
-    return arm7rr(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p)
+    return arm7rr(sub, n_obs=n_obs, horizon=t0 + width, t_min=t0, params=p, attempt=attempt)
 
 
 def self_pairs_for(prob: Problem) -> np.ndarray:
@@ -333,6 +343,20 @@ def with_static(prob: Problem, boxes: np.ndarray | None = None) -> Problem:
 
 def arm6static(seed: int, **kw) -> Problem:
     return with_static(arm6(seed, **kw))
+
+
+def redraw_until(make, accept, max_attempts: int = 64):
+    """The first of make(0), make(1), ... (the same obstacles, start and goal
+    drawn again from the attempt's own stream) that accept() takes, and the
+    attempt index; (None, max_attempts) if none.  The acceptance test is the
+    caller's: this module decides nothing about validity.  Evaluation sets use
+    it to keep only problems whose start is free at t = 0 and whose goal is
+    free at some goal-grid time, as the paper assumes of its queries."""
+    for a in range(max_attempts):
+        prob = make(a)
+        if accept(prob):
+            return prob, a
+    return None, max_attempts
 
 
 WORKLOADS = {"disc2d": disc2d, "arm6": arm6, "arm7rr": arm7rr, "mixed": mixed, "arm6static": arm6static}

@@ -34,6 +34,15 @@ def _no_recycling(prob):
     return prob
 
 
+def _tiny_pools(prob, p_new=0.5):
+    """Pools of a few dozen nodes, so that inserts are dropped within a few
+    iterations; a raised p_new gives many two-slot (virtual-root) claims."""
+    prob.params.cap_fwd = 60
+    prob.params.cap_bwd = 9
+    prob.params.p_new = p_new
+    return prob
+
+
 def _to_np(s):
     return {k: v.cpu().numpy() for k, v in s.items()}
 
@@ -63,9 +72,18 @@ PROBS = [
     # self-collision and fixed boxes switched on
     ("arm6-static-ir", lambda: _small(scenes.arm6static(8), 1024, groups=8)),
     ("arm7-static-rr", lambda: _small(scenes.with_static(scenes.arm7rr(30, n_obs=8)), 1024, groups=16)),
+    # pools that fill up: dropped inserts (a suffix per pool), two-slot
+    # virtual-root claims at the boundary
+    ("disc2d-capacity", lambda: _tiny_pools(_small(scenes.disc2d(1), 256))),
+    ("arm6-capacity", lambda: _tiny_pools(_small(scenes.arm6(2), 512, groups=8))),
+    # the root-recycling workload at its own shape: 7 DOF, 60 spheres, 32
+    # obstacles on 16 waypoints, 64 slots, 8192 samples per iteration
+    ("arm7-rr-full", lambda: scenes.arm7rr(2)),
 ]
 # largest fraction of workers with an exempt decision that may end differently
-MAX_EXEMPT_DIFF = {"arm6-ir-grazing": 0.5}
+# (measured on MI355X: at most 0.83 %, disc2d-rr; 0 of 4452 exempt workers in
+# the grazing case)
+MAX_EXEMPT_DIFF = 0.02
 
 
 @pytest.mark.parametrize("name,make", PROBS, ids=[p[0] for p in PROBS])
@@ -131,7 +149,14 @@ def _compare_batch(prob, s, g, r, counts=None):
                 n_ex_diff += 1
                 pool_diverged.add(pool)
             continue
-        assert g["status"][w] == r["status"][w], (w, g["status"][w], r["status"][w])
+        if pool in pool_diverged and g["status"][w] in (2, 3) and r["status"][w] in (2, 3):
+            # an earlier exempt worker of this pool claimed a different number
+            # of slots on the two sides, so where the pool fills up the
+            # claims of later workers end at different offsets
+            if g["status"][w] != r["status"][w]:
+                continue
+        else:
+            assert g["status"][w] == r["status"][w], (w, g["status"][w], r["status"][w])
         if r["status"][w] < 2:
             continue
         if pool in pool_diverged and appended(pool, r["parent"][w]):
@@ -159,7 +184,7 @@ def test_extend_lockstep_resync(oracle_lib, name, make):
     banner("extend %s" % name)
     gp = Problem(prob)
     op = oracle_lib.Planner(prob)
-    total_ex = total_diff = total = 0
+    total_ex = total_diff = total = n_dropped = 0
     for it in range(12):
         st = _resync(gp, op, prob)
         s_dev = gp.sample(it)
@@ -181,10 +206,15 @@ def test_extend_lockstep_resync(oracle_lib, name, make):
             else:
                 assert not math.isfinite(gi["U"])
             assert np.array_equal(gp.export()["counts"], op.counts())
-    banner("%s: %d workers, %d exempt, %d exempt with a different outcome" % (name, total, total_ex, total_diff))
+            assert bool(gi["overflow"]) == bool(oi["overflow"])
+        n_dropped += int((g["status"] == 3).sum())
+    if name.endswith("capacity"):
+        assert n_dropped > 0, "the pools never filled up"
+    banner("%s: %d workers, %d exempt, %d exempt with a different outcome, %d dropped" % (
+        name, total, total_ex, total_diff, n_dropped))
     assert total > 0
     assert total_ex <= 0.5 * total
-    assert total_diff <= MAX_EXEMPT_DIFF.get(name, 0.05) * total, (total_diff, total)
+    assert total_diff <= MAX_EXEMPT_DIFF * total, (total_diff, total)
 
 
 PLAN_CASES = [
@@ -300,3 +330,141 @@ def test_extension_paths_agree(make):
         assert np.array_equal(x, states[0][1])
         assert np.array_equal(par, states[0][2])
         assert w["edges"] == states[0][3]["edges"] and w["edge_states"] == states[0][3]["edge_states"]
+
+
+def _iterate_until_solved(gp, max_iters):
+    for it in range(max_iters):
+        gp.iterate(1)
+        inf = gp.info()
+        if math.isfinite(inf["U"]):
+            return it + 1, inf
+    return max_iters, gp.info()
+
+
+@pytest.mark.parametrize("name,make", [
+    ("disc2d-ir", lambda: _small(scenes.disc2d(3, t_min=0.0), 512)),
+    ("arm6-ir", lambda: _small(scenes.arm6(2), 1024, groups=8)),
+], ids=["disc2d-ir", "arm6-ir"])
+def test_interval_root_after_improvement(oracle_lib, name, make):
+    """Alg. 2's update on a drop of U, done by the device inside the publish
+    step: the repartition below Ubar = min(H, U) (uniform intervals and
+    guided shares, Sec. IV-B, Fig. 2(b)) equals the oracle's; the next
+    samples (root times drawn from the new partition, groups without an
+    active tree) equal the oracle's; the next extend batch, where trees
+    rooted at T >= U no longer take part, agrees in lockstep."""
+    from paper_2609_30533_amd.lib import Problem
+    prob = make()
+    banner("interval root after improvement %s" % name)
+    gp = Problem(prob)
+    op = oracle_lib.Planner(prob)
+    o = oracle_lib.Oracle(prob)
+    n, inf = _iterate_until_solved(gp, 300)
+    assert math.isfinite(inf["U"]), "no incumbent within 300 iterations"
+    banner("%s: U %.6f after %d iterations (L %.4f, H %.4f)" % (name, inf["U"], n, inf["L"], inf["H"]))
+    assert inf["U"] < inf["H"]
+    st = _resync(gp, op, prob)
+    I1, p1 = gp.partition()
+    I2, p2 = op.partition()
+    np.testing.assert_allclose(I1, I2, rtol=1e-12, atol=1e-12)
+    assert abs(I1[-1, 1] - min(inf["H"], inf["U"])) < 1e-12
+    for a, b in zip(p1, p2):
+        assert a.shape == b.shape
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+    # the groups' guided shares are equal and lie below Ubar
+    q = [float((pc[:, 1] - pc[:, 0]).sum()) if len(pc) else 0.0 for pc in p1]
+    assert np.allclose(q, q[0], atol=1e-9)
+    assert all(pc[:, 1].max() <= inf["U"] + 1e-12 for pc in p1 if len(pc))
+    B = prob.params.batch
+    it = int(inf["iter"])
+    s = _to_np(gp.sample(it))
+    r = op.sample(it, B)
+    assert np.array_equal(s["dir"], r["dir"]) and np.array_equal(s["grp"], r["grp"])
+    np.testing.assert_allclose(s["T"], r["T"], rtol=1e-6, atol=1e-6)
+    assert np.all(s["T"] < inf["U"] + 1e-6)
+    diff = np.where(s["flags"] != r["flags"])[0]
+    for i in diff:
+        _, m = o.state_valid(np.r_[prob.q_goal, r["T"][i]])
+        qq = r["qr"][:, i]
+        lo = np.linalg.norm(qq - prob.q_start) / prob.v_max
+        hi = r["T"][i] - np.linalg.norm(qq - prob.q_goal) / prob.v_max
+        assert abs(m) <= MARGIN or abs(hi - lo) <= 1e-5 * max(1.0, abs(hi)), (i, s["flags"][i], r["flags"][i])
+    assert len(diff) <= 0.01 * B
+    # one extend batch after the drop, in lockstep
+    s_dev = gp.sample(it)
+    s = _to_np(s_dev)
+    g = _to_np(gp.extend(s_dev))
+    sr = dict(dir=s["dir"], flags=s["flags"], grp=s["grp"], T=s["T"].astype(np.float64),
+              qr=s["qr"].astype(np.float64), tr=s["tr"].astype(np.float64))
+    rr = op.extend(sr)
+    n_ex, n_diff = _compare_batch(prob, s, g, rr, st["counts"])
+    banner("%s: after-drop batch, %d exempt, %d differing" % (name, n_ex, n_diff))
+    assert n_diff <= 0.05 * B
+
+
+def test_interval_root_termination(oracle_lib):
+    """Alg. 2 stops once L >= min(H, U): with an incumbent at U = L imported
+    into both sides, no worker runs (every sample is skipped, the trees do
+    not change) and the planning loop returns at its first check."""
+    from paper_2609_30533_amd.lib import Problem
+    prob = _small(scenes.disc2d(3, t_min=0.0), 512)
+    gp = Problem(prob)
+    op = oracle_lib.Planner(prob)
+    n, inf = _iterate_until_solved(gp, 300)
+    assert math.isfinite(inf["U"])
+    st = gp.export()
+    L = inf["L"]
+    gp.import_state(st["counts"], st["x"], st["parent"], st["cost"], st["rootT"], L, inf["C"], inf["inc_fwd"],
+                    inf["inc_bwd"], inf["iter"])
+    op.import_state(st["counts"], st["x"].astype(np.float64), st["parent"], st["cost"].astype(np.float64),
+                    st["rootT"].astype(np.float64), L, inf["C"], inf["inc_fwd"], inf["inc_bwd"], inf["iter"])
+    s = _to_np(gp.sample(int(inf["iter"])))
+    r = op.sample(int(inf["iter"]))
+    assert np.all(s["flags"] & 1) and np.all(r["flags"] & 1)
+    gp.iterate(8)
+    assert np.array_equal(gp.export()["counts"], st["counts"])
+    it0 = op.info()["iter"]
+    op.run(8)
+    assert op.info()["iter"] == it0
+    it_before = gp.info()["iter"]
+    res = gp.plan(max_iters=400, iters_per_sync=4)
+    assert res["iterations"] <= it_before + 4
+    assert np.array_equal(gp.export()["counts"], st["counts"])
+
+
+def test_trivial_case_on_device(oracle_lib):
+    """q_s = q_g with a free start and arrival at time 0 allowed is the
+    trivial case (Alg. 2 / Alg. 3 return the one-state path); with the
+    arrival range starting later the problem is planned as usual."""
+    from paper_2609_30533_amd import lib
+    for variant in (0, 1):
+        prob = scenes.disc2d(0, params=scenes.Params(variant=variant, n_groups=4 if variant == 0 else 8))
+        _small(prob, 256)
+        prob.q_goal = prob.q_start.copy()
+        prob.t_min = 0.0
+        prob.wp[:, :, 1:3] = 50.0
+        gp = lib.Problem(prob)
+        res = gp.plan(max_iters=20, iters_per_sync=4)
+        assert res["rc"] == lib.ST_TRIVIAL
+        assert res["states"].shape == (1, 3) and res["U"] == 0.0 and res["C"] == 0.0
+        assert oracle_lib.Planner(prob).run(5) == 2
+        prob.t_min = 2.0
+        gp2 = lib.Problem(prob)
+        res2 = gp2.plan(max_iters=80, iters_per_sync=4)
+        assert res2["rc"] == 0 and res2["U"] >= 2.0
+        ok, msg = oracle_lib.Oracle(prob).validate_path(res2["states"], res2["U"], res2["C"], rel_tol=1e-4)
+        assert ok, msg
+
+
+def test_capacity_exhausted_is_reported(oracle_lib):
+    """Pools too small for any path: the planner drops inserts, reports the
+    overflow, and st_plan ends with ST_ECAPACITY instead of a silent
+    failure; the trees stay within their capacities."""
+    from paper_2609_30533_amd import lib
+    prob = _small(scenes.arm6(2), 512, cap_f=24, cap_b=6, groups=8)
+    gp = lib.Problem(prob)
+    res = gp.plan(max_iters=24, iters_per_sync=4)
+    inf = gp.info()
+    assert inf["overflow"] == 1
+    assert res["rc"] == lib.ST_ECAPACITY and res["states"] is None
+    c = gp.export()["counts"]
+    assert c[0] <= 24 and np.all(c[1:] <= 6)
