@@ -228,6 +228,19 @@ int st_check_states(st_problem *p, int64_t M, const float *x, uint8_t *free_out,
 int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
                    int32_t *first_hit, void *stream);
 
+/* st_check_edges for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * check and results, with the pipeline's work lists in a fixed device array
+ * of the library instead of buffers it allocates, so the call allocates
+ * nothing (host or device).  E <= ST_NOALLOC_MAX_EDGES, else ST_EINVAL.  The
+ * array (about 8.6 MB) is held on every device the call runs on until the
+ * process ends; all calls on one device share it, so calls that overlap on a
+ * device (different streams or threads) race and must be serialised by the
+ * caller.  Inputs and outputs as for st_check_edges.  Async on stream. */
+#define ST_NOALLOC_MAX_EDGES 65536
+int st_check_edges_noalloc(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
+                           int32_t *first_hit, void *stream);
+
 /* Exact continuous check of edges for a translating robot (ST_ROBOT_TRANSLATE):
  * the edge's time span is cut where an obstacle changes trajectory segment;
  * on each piece robot and obstacle move linearly and every sphere pair's

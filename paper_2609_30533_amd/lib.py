@@ -93,7 +93,9 @@ EXPORTS = [
     "st_mlp_create", "st_mlp_destroy", "st_mlp_param_count", "st_mlp_params", "st_mlp_grads", "st_mlp_forward",
     "st_mlp_loss", "st_mlp_backward", "st_mlp_adam", "st_proposal_set",
     "st_path_get", "st_plan_sequence", "st_batch_create", "st_batch_destroy", "st_batch_iterate", "st_batch_plan",
+    "st_check_edges_noalloc",
 ]
+NOALLOC_MAX_EDGES = 65536
 NO_INT_RESULT = ("st_problem_destroy", "st_path_free", "st_last_error", "st_mlp_destroy", "st_mlp_param_count",
                  "st_batch_destroy")
 STAGES = ["sample", "nearest", "steer", "edge_check", "insert", "bridge_select", "bridge_check", "publish"]
@@ -119,6 +121,7 @@ def load():
     L.st_problem_reset.argtypes = [vp]
     L.st_check_states.argtypes = [vp, i64, vp, vp, vp]
     L.st_check_edges.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.st_check_edges_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp]
     L.st_nearest.argtypes = [vp, i32, i32, i32, i64, vp, vp, vp, vp]
     L.st_sample_batch.argtypes = [vp, i64, i64, C.POINTER(Samples), vp]
     L.st_extend_batch.argtypes = [vp, i64, C.POINTER(Samples), C.POINTER(ExtendOut), vp]
@@ -288,6 +291,13 @@ class Problem:
         _check(self.L.st_check_edges(self.h, E, _dptr(xa), _dptr(xb), _dptr(free), _dptr(fh), _stream(stream)),
                "st_check_edges")
         return free, fh
+
+    def check_edges_noalloc(self, xa, xb, free, first_hit=None, stream=None):
+        """st_check_edges_noalloc into caller-provided outputs (E <= NOALLOC_MAX_EDGES)."""
+        E = xa.shape[0]
+        _check(self.L.st_check_edges_noalloc(self.h, E, _dptr(xa), _dptr(xb), _dptr(free), _dptr(first_hit),
+                                             _stream(stream)), "st_check_edges_noalloc")
+        return free, first_hit
 
     def check_edges_continuous(self, xa, xb, stream=None):
         """Exact continuous check (translating robots): (free, least clearance)."""
