@@ -188,6 +188,10 @@ typedef struct st_info {
     int64_t total_cap;        /* cap_fwd + N cap_bwd */
     int32_t n_pools;          /* 1 + N */
     int64_t first_iter;       /* iteration of the first incumbent, -1 if none */
+    /* launch shape (the batch of many problems reads these at st_batch_create) */
+    int32_t batch;            /* samples per iteration B */
+    int32_t obstacle_tile;    /* obstacles per register tile of the collision kernels */
+    int32_t lanes_extension, lanes_bridge, lanes_check; /* lanes per edge chunk (st_set_tuning) */
 } st_info;
 
 /* ---- lifecycle -------------------------------------------------------- */
@@ -321,6 +325,20 @@ void st_path_free(st_path *path);
  * Synchronous. */
 int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals, const st_budget *budget,
                      st_path *out);
+
+/* Goal sequences of many problems planned together (Sec. III, as
+ * st_plan_sequence does for one): leg i of every problem that has an i-th goal
+ * and has not failed is planned in one batch of many problems (st_batch_*),
+ * each leg with the budget (applied to the whole batch of that leg), and the
+ * legs are joined in absolute time.  descs: host [P]; m: host [P] goal
+ * counts (>= 1); goals: host [P] pointers to host [m[k]][d_k] (desc->q_goal is
+ * ignored); outs: host [P], library-allocated paths (free each with
+ * st_path_free); rcs: host [P] per-problem result (ST_OK, ST_NO_SOLUTION
+ * when some leg found no path or no horizon was left, ST_ECAPACITY).  Returns
+ * ST_OK when every problem was processed, else the first error.
+ * Synchronous. */
+int st_plan_sequence_batch(const st_problem_desc *descs, int32_t P, const int32_t *m, const double *const *goals,
+                           const st_budget *budget, st_path *outs, int32_t *rcs);
 
 /* The current incumbent path of a problem (host, library-allocated; free with
  * st_path_free).  Returns ST_OK, ST_NO_SOLUTION, or ST_ECAPACITY as st_plan

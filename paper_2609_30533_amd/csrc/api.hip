@@ -9,6 +9,7 @@
 #include <chrono>
 #include <numeric>
 
+#include "pipeline.hpp"
 #include "st_internal.hpp"
 
 namespace st {
@@ -674,6 +675,63 @@ int st_check_edges(st_problem *p, int64_t E, const float *xa, const float *xb, u
     return ST_OK;
 }
 
+}  // extern "C"
+
+namespace st {
+
+// One query of a goal sequence (Sec. III): leg i starts at the previous goal
+// with local time 0 at the previous arrival T, the obstacle trajectories
+// shifted by T and the remaining horizon; only the last goal keeps the
+// arrival range's lower end.  The description points into this object's own
+// waypoint copy.
+struct SequenceLeg {
+    std::vector<double> wp;
+    st_problem_desc D;
+    // false when no horizon is left
+    bool make(const st_problem_desc *desc, int32_t m, const double *goals, int i, const double *q_start,
+              double T) {
+        const int d = desc->dof, O = desc->n_obstacles, Wm = desc->max_waypoints;
+        wp.assign(O > 0 ? (size_t)O * Wm * 4 : 1, 0.0);
+        D = *desc;
+        for (int o = 0; o < O; ++o)
+            for (int k = 0; k < Wm; ++k) {
+                const size_t r = ((size_t)o * Wm + k) * 4;
+                wp[r] = desc->waypoints[r] - T;
+                for (int c = 1; c < 4; ++c) wp[r + c] = desc->waypoints[r + c];
+            }
+        if (O > 0) D.waypoints = wp.data();
+        D.q_start = q_start;
+        D.q_goal = goals + (size_t)i * d;
+        D.t_max = desc->t_max - T;
+        D.t_min = i + 1 == m ? std::max(0.0, desc->t_min - T) : 0.0;
+        D.params.problem_id = desc->params.problem_id + 7919u * (uint32_t)i;
+        return D.t_max > 0.0;
+    }
+};
+
+// Appends a leg's path (local time) to an absolute-time path; a leg starts
+// where the previous one ended, so its first state is dropped after leg 0.
+static void append_leg(std::vector<double> &states, const st_path &leg, int d, int i, double T) {
+    for (int64_t s = (i > 0 ? 1 : 0); s < leg.n_states; ++s) {
+        for (int j = 0; j < d; ++j) states.push_back(leg.states[s * (d + 1) + j]);
+        states.push_back(leg.states[s * (d + 1) + d] + T);
+    }
+}
+
+static int finish_sequence(st_path *out, const std::vector<double> &states, int d, double T, double C) {
+    out->n_states = (int64_t)(states.size() / (d + 1));
+    out->states = (double *)malloc(sizeof(double) * std::max<size_t>(states.size(), 1));
+    if (!out->states) return fail(ST_ENOMEM, "goal sequence: out of host memory");
+    memcpy(out->states, states.data(), sizeof(double) * states.size());
+    out->arrival = T;
+    out->length = C;
+    return ST_OK;
+}
+
+}  // namespace st
+
+extern "C" {
+
 int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals, const st_budget *budget,
                      st_path *out) {
     if (!desc || m < 1 || !goals || !budget || !out) return fail(ST_EINVAL, "st_plan_sequence: bad arguments");
@@ -687,40 +745,24 @@ int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals
     auto ms_since = [&]() {
         return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     };
-    const int O = desc->n_obstacles, Wm = desc->max_waypoints;
-    std::vector<double> wp(O > 0 ? (size_t)O * Wm * 4 : 1);
     std::vector<double> qs(desc->q_start, desc->q_start + d);
     std::vector<double> states;  // absolute-time path, rows of d + 1
     double T = 0.0, C = 0.0;
     int64_t iters = 0;
     int rc = ST_OK;
+    SequenceLeg L;
     for (int i = 0; i < m && rc == ST_OK; ++i) {
-        // leg i: local time 0 at the previous arrival, obstacles shifted by it,
-        // the remaining horizon; only the last goal keeps the arrival range's
-        // lower end
-        st_problem_desc D = *desc;
-        for (int o = 0; o < O; ++o)
-            for (int k = 0; k < Wm; ++k) {
-                const size_t r = ((size_t)o * Wm + k) * 4;
-                wp[r] = desc->waypoints[r] - T;
-                for (int c = 1; c < 4; ++c) wp[r + c] = desc->waypoints[r + c];
-            }
-        if (O > 0) D.waypoints = wp.data();
-        D.q_start = qs.data();
-        D.q_goal = goals + (size_t)i * d;
-        D.t_max = desc->t_max - T;
-        D.t_min = i + 1 == m ? std::max(0.0, desc->t_min - T) : 0.0;
-        D.params.problem_id = desc->params.problem_id + 7919u * (uint32_t)i;
-        if (!(D.t_max > 0.0)) {
+        if (!L.make(desc, m, goals, i, qs.data(), T)) {
             rc = ST_NO_SOLUTION;
             break;
         }
         st_problem *p = nullptr;
-        if ((rc = st_problem_create(&D, &p)) != ST_OK) break;
+        if ((rc = st_problem_create(&L.D, &p)) != ST_OK) break;
         st_path leg;
         const int lr = st_plan(p, budget, &leg);
         st_problem_destroy(p);
         if (lr < 0) {
+            st_path_free(&leg);
             rc = lr;
             break;
         }
@@ -729,11 +771,7 @@ int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals
             rc = ST_NO_SOLUTION;
             break;
         }
-        // append in absolute time; a leg starts where the previous one ended
-        for (int64_t s = (i > 0 ? 1 : 0); s < leg.n_states; ++s) {
-            for (int j = 0; j < d; ++j) states.push_back(leg.states[s * (d + 1) + j]);
-            states.push_back(leg.states[s * (d + 1) + d] + T);
-        }
+        append_leg(states, leg, d, i, T);
         T += leg.arrival;
         C += leg.length;
         iters += leg.iterations;
@@ -747,13 +785,106 @@ int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals
     out->iterations = iters;
     out->total_ms = ms_since();
     if (rc != ST_OK) return rc;
-    out->n_states = (int64_t)(states.size() / (d + 1));
-    out->states = (double *)malloc(sizeof(double) * states.size());
-    if (!out->states) return fail(ST_ENOMEM, "st_plan_sequence: out of host memory");
-    memcpy(out->states, states.data(), sizeof(double) * states.size());
-    out->arrival = T;
-    out->length = C;
-    return ST_OK;
+    return finish_sequence(out, states, d, T, C);
+}
+
+int st_plan_sequence_batch(const st_problem_desc *descs, int32_t P, const int32_t *m, const double *const *goals,
+                           const st_budget *budget, st_path *outs, int32_t *rcs) {
+    if (!descs || P < 1 || P > 4096 || !m || !goals || !budget || !outs || !rcs)
+        return fail(ST_EINVAL, "st_plan_sequence_batch: bad arguments");
+    for (int k = 0; k < P; ++k)
+        if (m[k] < 1 || !goals[k]) return fail(ST_EINVAL, "st_plan_sequence_batch: problem %d has no goals", k);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto ms_since = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    std::vector<std::vector<double>> qs(P), states(P);
+    std::vector<double> T(P, 0.0), C(P, 0.0);
+    int32_t max_m = 0;
+    for (int k = 0; k < P; ++k) {
+        memset(&outs[k], 0, sizeof outs[k]);
+        outs[k].dof = descs[k].dof;
+        outs[k].first_solution_iter = -1;
+        outs[k].arrival = INFINITY;
+        outs[k].length = INFINITY;
+        qs[k].assign(descs[k].q_start, descs[k].q_start + descs[k].dof);
+        rcs[k] = ST_OK;
+        max_m = std::max(max_m, m[k]);
+    }
+    int rc = ST_OK;
+    for (int i = 0; i < max_m && rc == ST_OK; ++i) {
+        // leg i of every problem still on its way, planned as one batch
+        std::vector<int> who;
+        std::vector<SequenceLeg> legs(P);
+        std::vector<st_problem *> hs;
+        for (int k = 0; k < P && rc == ST_OK; ++k) {
+            if (i >= m[k] || rcs[k] != ST_OK) continue;
+            if (!legs[k].make(&descs[k], m[k], goals[k], i, qs[k].data(), T[k])) {
+                rcs[k] = ST_NO_SOLUTION;
+                continue;
+            }
+            st_problem *h = nullptr;
+            const int r = st_problem_create(&legs[k].D, &h);
+            if (r != ST_OK) {
+                rc = r;
+                break;
+            }
+            who.push_back(k);
+            hs.push_back(h);
+        }
+        if (rc == ST_OK && !hs.empty()) {
+            st_batch *b = nullptr;
+            rc = st_batch_create(hs.data(), (int32_t)hs.size(), 4, &b);
+            if (rc == ST_OK) {
+                st_batch_result br;
+                memset(&br, 0, sizeof br);
+                rc = st_batch_plan(b, budget, &br);
+                st_batch_destroy(b);
+            }
+            for (size_t j = 0; j < who.size() && rc == ST_OK; ++j) {
+                const int k = who[j];
+                st_path leg;
+                const int lr = st_path_get(hs[j], &leg);
+                if (lr < 0 && lr != ST_ECAPACITY) {
+                    st_path_free(&leg);
+                    rc = lr;
+                    break;
+                }
+                if (lr != ST_OK || leg.n_states < 1) {
+                    // a trivial leg (start = goal, arrival 0 allowed) has one state
+                    st_problem *h = hs[j];
+                    bool start_free = false, trivial = false;
+                    if (lr == ST_NO_SOLUTION && start_check(h, &start_free, &trivial) == ST_OK && trivial) {
+                        for (int c = 0; c < descs[k].dof; ++c) states[k].push_back(qs[k][c]);
+                        states[k].push_back(T[k]);
+                        if (i + 1 < m[k]) qs[k].assign(goals[k] + (size_t)i * descs[k].dof,
+                                                       goals[k] + (size_t)(i + 1) * descs[k].dof);
+                        st_path_free(&leg);
+                        continue;
+                    }
+                    rcs[k] = lr == ST_ECAPACITY ? ST_ECAPACITY : ST_NO_SOLUTION;
+                    st_path_free(&leg);
+                    continue;
+                }
+                const int d = descs[k].dof;
+                append_leg(states[k], leg, d, i, T[k]);
+                T[k] += leg.arrival;
+                C[k] += leg.length;
+                outs[k].iterations += leg.iterations;
+                st_path_free(&leg);
+                qs[k].assign(goals[k] + (size_t)i * d, goals[k] + (size_t)(i + 1) * d);
+            }
+        }
+        for (st_problem *h : hs) st_problem_destroy(h);
+    }
+    for (int k = 0; k < P; ++k) {
+        outs[k].total_ms = ms_since();
+        if (rc == ST_OK && rcs[k] == ST_OK) {
+            const int r = finish_sequence(&outs[k], states[k], descs[k].dof, T[k], C[k]);
+            if (r != ST_OK) rc = r;
+        }
+    }
+    return rc;
 }
 
 int st_check_edges_continuous(st_problem *p, int64_t E, const float *xa, const float *xb, uint8_t *free_out,
@@ -785,6 +916,11 @@ int st_get_info(st_problem *p, st_info *out) {
     out->total_cap = p->tree.total;
     out->n_pools = p->tree.n_pools;
     out->first_iter = pl.first_iter;
+    out->batch = p->prm.batch;
+    out->obstacle_tile = p->sc.ot;
+    out->lanes_extension = 1 << p->tune_ext;
+    out->lanes_bridge = 1 << p->tune_br;
+    out->lanes_check = 1 << p->tune_api;
     return ST_OK;
 }
 

@@ -80,7 +80,9 @@ class Info(C.Structure):
     _fields_ = [("U", C.c_double), ("C", C.c_double), ("inc_fwd", C.c_int64), ("inc_bwd", C.c_int64),
                 ("L", C.c_double), ("H", C.c_double), ("k_lo", C.c_int64), ("k_hi", C.c_int64),
                 ("iter", C.c_int64), ("overflow", C.c_int32), ("n_active", C.c_int32), ("total_cap", C.c_int64),
-                ("n_pools", C.c_int32), ("first_iter", C.c_int64)]
+                ("n_pools", C.c_int32), ("first_iter", C.c_int64), ("batch", C.c_int32),
+                ("obstacle_tile", C.c_int32), ("lanes_extension", C.c_int32), ("lanes_bridge", C.c_int32),
+                ("lanes_check", C.c_int32)]
 
 
 # Every symbol the header declares (used by the load test).
@@ -93,7 +95,7 @@ EXPORTS = [
     "st_mlp_create", "st_mlp_destroy", "st_mlp_param_count", "st_mlp_params", "st_mlp_grads", "st_mlp_forward",
     "st_mlp_loss", "st_mlp_backward", "st_mlp_adam", "st_proposal_set",
     "st_path_get", "st_plan_sequence", "st_batch_create", "st_batch_destroy", "st_batch_iterate", "st_batch_plan",
-    "st_check_edges_noalloc",
+    "st_check_edges_noalloc", "st_plan_sequence_batch",
 ]
 NOALLOC_MAX_EDGES = 65536
 NO_INT_RESULT = ("st_problem_destroy", "st_path_free", "st_last_error", "st_mlp_destroy", "st_mlp_param_count",
@@ -146,6 +148,7 @@ def load():
     L.st_path_get.argtypes = [vp, C.POINTER(Path)]
     L.st_plan_sequence.argtypes = [C.POINTER(Desc), i32, C.POINTER(C.c_double), C.POINTER(Budget), C.POINTER(Path)]
     L.st_check_edges_continuous.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+    L.st_plan_sequence_batch.argtypes = [C.POINTER(Desc), i32, vp, vp, C.POINTER(Budget), C.POINTER(Path), vp]
     L.st_batch_create.argtypes = [C.POINTER(vp), i32, i32, C.POINTER(vp)]
     L.st_batch_destroy.argtypes = [vp]
     L.st_batch_destroy.restype = None
@@ -238,7 +241,7 @@ def plan_sequence(prob: scenes.Problem, goals, max_iters=0, max_ms=0.0, stop_at_
     b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
     path = Path()
     rc = _check(L.st_plan_sequence(C.byref(D), int(g.shape[0]), g.ctypes.data_as(C.POINTER(C.c_double)),
-                                   C.byref(b), C.byref(path)), "st_plan_sequence")
+                                   C.byref(b), C.byref(path)), "st_plan_sequence", allow=(ST_ECAPACITY,))
     try:
         n = path.n_states
         d = prob.d
@@ -248,6 +251,44 @@ def plan_sequence(prob: scenes.Problem, goals, max_iters=0, max_ms=0.0, stop_at_
     finally:
         L.st_path_free(C.byref(path))
         del keep
+
+
+def plan_sequence_batch(probs, goal_lists, max_iters=0, max_ms=0.0, stop_at_first=False, iters_per_sync=0,
+                        problem_ids=None):
+    """st_plan_sequence_batch: every problem visits its goals [m_k][d_k] in
+    order; leg i of all problems runs as one batch.  Returns one dict per
+    problem (rc, states in absolute time, U, C, iterations)."""
+    L = load()
+    P = len(probs)
+    ids = problem_ids if problem_ids is not None else list(range(P))
+    descs = (Desc * P)()
+    keep = []
+    for k, (p, pid) in enumerate(zip(probs, ids)):
+        D, kp = make_desc(p, pid)
+        descs[k] = D
+        keep.append(kp)
+    gl = [np.ascontiguousarray(g, dtype=np.float64) for g in goal_lists]
+    m = np.array([g.shape[0] for g in gl], dtype=np.int32)
+    gptr = (C.POINTER(C.c_double) * P)(*[g.ctypes.data_as(C.POINTER(C.c_double)) for g in gl])
+    outs = (Path * P)()
+    rcs = np.zeros(P, dtype=np.int32)
+    b = Budget(max_iters, max_ms, 1 if stop_at_first else 0, iters_per_sync)
+    _check(L.st_plan_sequence_batch(descs, P, _ptr(m), C.cast(gptr, C.c_void_p), C.byref(b), outs, _ptr(rcs)),
+           "st_plan_sequence_batch")
+    res = []
+    try:
+        for k in range(P):
+            path = outs[k]
+            n, d = path.n_states, probs[k].d
+            states = np.ctypeslib.as_array(path.states, shape=(n * (d + 1),)).reshape(n, d + 1).copy() \
+                if (n > 0 and rcs[k] == ST_OK) else None
+            res.append(dict(rc=int(rcs[k]), states=states, U=path.arrival, C=path.length,
+                            iterations=path.iterations))
+    finally:
+        for k in range(P):
+            L.st_path_free(C.byref(outs[k]))
+        del keep, gl
+    return res
 
 
 class Problem:

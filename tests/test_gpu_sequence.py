@@ -64,3 +64,34 @@ def test_single_goal_sequence_equals_plan():
     assert r1["rc"] == r2["rc"]
     if r2["rc"] == 0:
         assert r1["U"] == r2["U"] and np.array_equal(r1["states"], r2["states"])
+
+
+def test_goal_sequences_batched(oracle_lib):
+    """Goal sequences of many problems at once (leg i of every problem in one
+    batch): every returned path is re-validated in absolute time against the
+    unshifted scene, and with an iteration budget each problem's path equals
+    the one st_plan_sequence finds for it alone (a batch member's trees equal
+    the single run's, iteration for iteration)."""
+    from paper_2609_30533_amd.lib import plan_sequence, plan_sequence_batch
+    torch_cuda()
+    probs, goal_lists = [], []
+    for seed in range(8):
+        prob = scenes.disc2d(seed)
+        prob.params.batch = 256
+        prob.params.cap_fwd, prob.params.cap_bwd = 1 << 15, 1 << 12
+        probs.append(prob)
+        goal_lists.append(_goals(prob, 2 + seed % 3, seed))
+    banner("batched sequences: %d problems" % len(probs))
+    res = plan_sequence_batch(probs, goal_lists, max_iters=200, iters_per_sync=8)
+    ok = 0
+    for k, (prob, goals, r) in enumerate(zip(probs, goal_lists, res)):
+        single = plan_sequence(prob, goals, max_iters=200, iters_per_sync=8, problem_id=k)
+        assert r["rc"] == single["rc"], (k, r["rc"], single["rc"])
+        if r["rc"] != 0:
+            continue
+        ok += 1
+        _validate(oracle_lib, prob, r["states"], goals, r["U"])
+        assert np.array_equal(r["states"], single["states"]), k
+        assert r["U"] == single["U"]
+    banner("batched sequences: %d of %d solved" % (ok, len(probs)))
+    assert ok >= 5
