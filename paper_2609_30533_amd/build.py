@@ -26,17 +26,28 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
 
 
-def _headers():
-    return glob.glob(os.path.join(CSRC, "*.hpp")) + glob.glob(os.path.join(ROOT, "include", "*.h"))
+def _includes(path, seen=None):
+    """The library headers a source includes, directly or through other
+    headers (quoted includes resolved next to the including file)."""
+    seen = set() if seen is None else seen
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line.startswith("#include \""):
+                inc = os.path.normpath(os.path.join(os.path.dirname(path), line.split('"')[1]))
+                if os.path.exists(inc) and inc not in seen:
+                    seen.add(inc)
+                    _includes(inc, seen)
+    return seen
 
 
 def _stale(src, obj):
-    """An object is rebuilt when it is missing or older than its source or
-    any header of the library."""
+    """An object is rebuilt when it is missing or older than its source or a
+    header the source includes."""
     if not os.path.exists(obj):
         return True
     t = os.path.getmtime(obj)
-    return any(os.path.getmtime(f) > t for f in [src, *_headers()])
+    return any(os.path.getmtime(f) > t for f in [src, *_includes(src)])
 
 
 def build(verbose: bool = False, jobs: int = 8, incremental: bool = False) -> str:

@@ -191,6 +191,7 @@ static int batch_build(st_batch *b) {
             c.nb_items_br = std::max(c.nb_items_br, edge_br[m].nb_items);
             if (edge_ext[m].flat > 0) c.nb_flat = std::max(c.nb_flat, flat_blocks(edge_ext[m].E, edge_ext[m].flat));
             c.lds = std::max(c.lds, scene_lds_bytes(b->mem[m]->sc));
+            c.lds_sample = std::max(c.lds_sample, sample_lds_bytes(b->mem[m], nullptr));
         }
         ST_HIP(upload(b->owned, kv.second, &c.members));
         L.classes.push_back(c);

@@ -50,7 +50,10 @@ __device__ __forceinline__ int worker_pool(int8_t dir, int32_t grp) { return dir
 // with probability p_guided (when the guided windows below Ubar are not empty)
 // a portion of the group's guided share chosen in proportion to its length and
 // a uniform time inside it; otherwise uniform on I_g.
-__device__ double ir_root_time(const WindowsDev &w, const PlanDev *pl, int g, const uint32_t *u, float p_guided) {
+// The windows' lo, hi and cum arrays are read from wlo, whi, wcum (LDS when
+// the sampler staged them, else the device copies in w).
+__device__ double ir_root_time(const WindowsDev &w, const double *wlo, const double *whi, const double *wcum,
+                               const PlanDev *pl, int g, const uint32_t *u, float p_guided) {
     const double L = w.L, Ubar = pl->Ubar, G = pl->G;
     const int N = w.N;
     if (unit24f(u[1]) < p_guided && G > 0.0 && pl->jstar > 0) {
@@ -60,13 +63,13 @@ __device__ double ir_root_time(const WindowsDev &w, const PlanDev *pl, int g, co
         int lo = 0, hi = pl->jstar - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (w.cum[mid] <= c) lo = mid;
+            if (wcum[mid] <= c) lo = mid;
             else hi = mid - 1;
         }
         const int j = lo;
-        const double len = fmin(w.hi[j], Ubar) - w.lo[j];
-        const double a = fmax(c_lo, w.cum[j]), b = fmin(c_hi, w.cum[j] + len);
-        return w.lo[j] + (a - w.cum[j]) + unit24d(u[3]) * (b - a);
+        const double len = fmin(whi[j], Ubar) - wlo[j];
+        const double a = fmax(c_lo, wcum[j]), b = fmin(c_hi, wcum[j] + len);
+        return wlo[j] + (a - wcum[j]) + unit24d(u[3]) * (b - a);
     }
     const double width = (Ubar - L) / N;
     const double I0 = L + g * width, I1 = L + (g + 1) * width;
@@ -88,6 +91,16 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
     if (MULTI && (int)blockIdx.x >= a.nb) return;
     const SceneDev &sc = a.sc;
     const bool ir = a.variant == ST_INTERVAL_ROOT;
+    // interval root: the guided windows go to LDS behind the scene, so the
+    // binary search of a root time reads LDS, not device memory
+    const int nwl = ir ? a.nw_lds : 0;
+    double *wl = reinterpret_cast<double *>(lds + sc.lds_f4);
+    for (int i = threadIdx.x; i < nwl; i += blockDim.x) {
+        const double x0 = a.win.lo[i], x1 = a.win.hi[i], x2 = a.win.cum[i];
+        wl[i] = x0;
+        wl[nwl + i] = x1;
+        wl[2 * nwl + i] = x2;
+    }
     if (ir) stage_obstacles(sc, lds);
     constexpr int SL = sample_lanes<KIND>();
     const int64_t gt = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -164,7 +177,8 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
                 check_root = !(flags & ST_FLAG_SKIP);
             }
         } else {
-            T = (float)ir_root_time(a.win, pl, g, u, a.p_guided);
+            T = nwl > 0 ? (float)ir_root_time(a.win, wl, wl + nwl, wl + 2 * nwl, pl, g, u, a.p_guided)
+                        : (float)ir_root_time(a.win, a.win.lo, a.win.hi, a.win.cum, pl, g, u, a.p_guided);
             check_root = true;
         }
     } else if (act && dir == 1) {
@@ -519,9 +533,9 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     }
     if (!act) return;
     if (MODE == kScanBridge) {
-        a.pkey[(int64_t)blockIdx.y * a.pstride + q] =
+        a.pkey[(int64_t)q * a.pstride + blockIdx.y] =
             bi < 0 ? kNoKey : (((unsigned long long)__float_as_uint(bestT) << 32) | __float_as_uint(best));
-        a.pidx[(int64_t)blockIdx.y * a.pstride + q] = bi;
+        a.pidx[(int64_t)q * a.pstride + blockIdx.y] = bi;
     } else if (bi >= 0) {
         atomicMin(&a.keys[q], pack_key(best, bi));
     }
@@ -787,9 +801,9 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
     uint32_t bi = 0xffffffffu;
     if (adv) {
         for (int y = lane; y < a.nch; y += 64) {
-            const int32_t ii = k.br_idx[(int64_t)y * a.B + w];
+            const int32_t ii = k.br_idx[(int64_t)w * a.nch + y];
             if (ii < 0) continue;
-            const unsigned long long kk = k.br_key[(int64_t)y * a.B + w];
+            const unsigned long long kk = k.br_key[(int64_t)w * a.nch + y];
             if (kk < bk || (kk == bk && (uint32_t)ii < bi)) {
                 bk = kk;
                 bi = (uint32_t)ii;
@@ -1297,13 +1311,23 @@ SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const 
     a.t_max = p->t_max;
     a.out = out;
     a.nb = (int)((B * (p->sc.kind == kDH ? sample_lanes<kDH>() : 1) + 255) / 256);
+    (void)sample_lds_bytes(p, &a.nw_lds);
     return a;
+}
+
+size_t sample_lds_bytes(const st_problem *p, int32_t *nw_lds) {
+    const size_t scene = scene_lds_bytes(p->sc);
+    const int32_t nw = p->prm.variant == ST_INTERVAL_ROOT ? p->win.nw : 0;
+    // windows are staged while the whole stays within 64 KB of LDS
+    const bool fit = scene + (size_t)nw * 3 * sizeof(double) <= 64 * 1024;
+    if (nw_lds) *nw_lds = fit ? nw : 0;
+    return scene + (fit ? (size_t)nw * 3 * sizeof(double) : 0);
 }
 
 int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s) {
     prof_mark(p, kStSample, s);
     const SampleArgs a = make_sample_args(p, iter, B, out);
-    const size_t lds = scene_lds_bytes(p->sc);
+    const size_t lds = sample_lds_bytes(p, nullptr);
     dispatch_scene2(p->sc, [&](auto kind, auto ot, auto obs) {
         k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, false>
             <<<dim3(a.nb), dim3(256), lds, s>>>(a, nullptr, nullptr);
@@ -1396,7 +1420,7 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     sb.keys = nullptr;
     sb.pkey = w.br_key;
     sb.pidx = w.br_idx;
-    sb.pstride = B;
+    sb.pstride = nch_br;  // query-major partials: [query][slice]
     sb.nch = nch_br;
     BridgeArgs &ba = a.merge;
     ba.tree = p->tree;
@@ -1484,7 +1508,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     for (const BatchClass &c : L.classes) {
         dispatch_scene2(c.key, [&](auto kind, auto ot, auto obs) {
             k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, true>
-                <<<dim3(c.nb_sample, c.n), dim3(256), c.lds, s>>>(SampleArgs{}, L.sample, c.members);
+                <<<dim3(c.nb_sample, c.n), dim3(256), c.lds_sample, s>>>(SampleArgs{}, L.sample, c.members);
         });
     }
     ST_HIP(hipGetLastError());

@@ -19,6 +19,7 @@ struct SampleArgs {
     double t_min, t_max;  // arrival range (the learned histogram spans it)
     st_samples out;
     int32_t nb;           // blocks (many-problem launches)
+    int32_t nw_lds;       // guided windows staged in LDS after the scene (0: read from device memory)
 };
 
 struct PrepArgs {
@@ -131,6 +132,7 @@ struct BatchClass {
     int n;                  // members
     int nb_sample, nb_items_ext, nb_items_br, nb_flat;  // grid maxima over the members
     size_t lds;             // dynamic LDS, maximum over the members
+    size_t lds_sample;      // the sampler's (scene and guided windows), maximum over the members
 };
 
 // Device arrays of records (P problems) and grid maxima for one iteration of
@@ -158,6 +160,9 @@ int start_check(st_problem *p, bool *start_free, bool *trivial);
 int fetch_path(st_problem *p, hipStream_t s, st_path *out);
 st_samples work_samples_of(st_problem *p);
 size_t scene_lds_bytes(const SceneDev &sc);
+// Dynamic LDS of the sampler: the scene, then (interval root) the guided
+// windows lo, hi, cum as doubles when they fit.
+size_t sample_lds_bytes(const st_problem *p, int32_t *nw_lds);
 int nch_for_tiles(int tiles);
 int max_query_tiles(int64_t B, int n_sets);
 

@@ -15,7 +15,9 @@ import numpy as np
 from . import scenes
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_build", "libstprrtc.so")
+# STPRRTC_LIBRARY may name another build of the same library (A/B timing of
+# kernel variants); by default the in-tree build is loaded
+LIB_PATH = os.environ.get("STPRRTC_LIBRARY") or os.path.join(_HERE, "_build", "libstprrtc.so")
 
 ST_OK, ST_NO_SOLUTION, ST_TRIVIAL = 0, 1, 2
 ST_ECAPACITY = -4

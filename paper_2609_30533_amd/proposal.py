@@ -30,10 +30,15 @@ K_STATES = 16       # path states per training example
 TRAIN_SEED0 = 1_000_000  # training problems use seeds from here on; evaluation seeds stay below
 
 
-def harvest_problem(seed: int) -> scenes.Problem:
-    """A training problem of the 6-DOF arm workload with a smaller sample
-    count, so that many of them share the device."""
-    p = scenes.arm6(seed)
+def harvest_problem(seed: int):
+    """A training problem of the 6-DOF arm workload, drawn as the evaluation
+    problems are (start and goal redrawn until the library finds the start
+    free and some goal-grid time free), with a smaller sample count so that
+    many of them share the device; None when no draw is accepted."""
+    from .problems import eval_problem
+    p, _ = eval_problem("arm6", seed, max_attempts=16)
+    if p is None:
+        return None
     p.params.batch = 512
     p.params.cap_fwd = 1 << 16
     p.params.cap_bwd = 1 << 13
@@ -49,8 +54,10 @@ def harvest(n_paths: int, per_batch: int = 128, max_ms: float = 2500.0, seed0: i
     seed = seed0
     t0 = time.time()
     while len(out) < n_paths and time.time() - t0 < time_limit_s:
-        probs = [harvest_problem(seed + i) for i in range(per_batch)]
+        probs = [q for q in (harvest_problem(seed + i) for i in range(per_batch)) if q is not None]
         seed += per_batch
+        if not probs:
+            continue
         gps = [Problem(p, problem_id=i) for i, p in enumerate(probs)]
         b = Batch(gps)
         r = b.plan(max_ms=max_ms, stop_at_first=False)
@@ -167,6 +174,20 @@ class Proposal:
         return z
 
 
+def load_pairs(path):
+    """(problem, path) pairs saved by --save-paths: each problem is drawn
+    again from its seed (the same accepted start and goal)."""
+    z = np.load(path, allow_pickle=False)
+    out, off = [], 0
+    for seed, n in zip(z["seeds"], z["lengths"]):
+        st = z["states"][off:off + int(n)]
+        off += int(n)
+        p = harvest_problem(int(seed))
+        if p is not None:
+            out.append((p, {"states": st}))
+    return out
+
+
 def load_weights(path):
     return np.load(path, allow_pickle=False).astype(np.float32)
 
@@ -180,13 +201,24 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--out", required=True)
     ap.add_argument("--log", default=None)
+    ap.add_argument("--save-paths", default=None, help="also keep the harvested (seed, path) pairs (.npz)")
+    ap.add_argument("--seed0", type=int, default=TRAIN_SEED0, help="first training problem seed")
+    ap.add_argument("--with-paths", default=None,
+                    help="earlier harvested pairs (.npz from --save-paths) to train on as well")
     a = ap.parse_args(argv)
 
     def log(msg):
         print(msg, flush=True)
 
     t0 = time.time()
-    pairs = harvest(a.paths, a.per_batch, a.plan_ms, log=log, time_limit_s=a.harvest_s)
+    earlier = load_pairs(a.with_paths) if a.with_paths else []
+    pairs = harvest(max(a.paths - len(earlier), 0), a.per_batch, a.plan_ms, seed0=a.seed0, log=log,
+                    time_limit_s=a.harvest_s)
+    if a.save_paths:
+        np.savez_compressed(a.save_paths, seeds=np.array([p.seed for p, _ in pairs]),
+                            lengths=np.array([len(q["states"]) for _, q in pairs]),
+                            states=np.concatenate([q["states"] for _, q in pairs]))
+    pairs = earlier + pairs
     data = make_dataset(pairs)
     w, hist = train(data, steps=a.steps, log=log)
     np.save(a.out, w)
