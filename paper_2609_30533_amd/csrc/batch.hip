@@ -17,6 +17,7 @@
 #include <tuple>
 #include <vector>
 
+#include "edge_flat.hpp"
 #include "pipeline.hpp"
 
 namespace st {

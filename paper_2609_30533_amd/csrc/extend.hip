@@ -24,6 +24,7 @@
 #include <chrono>
 #include <vector>
 
+#include "edge_flat.hpp"
 #include "pipeline.hpp"
 #include "rng.hpp"
 #include "st_internal.hpp"
@@ -546,11 +547,15 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
 // ---------------------------------------------------------------------------
 
 
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av) {
-    const SteerArgs &a = MULTI ? av[blockIdx.y] : a0;
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.B) return;
+// Steering of worker w (all its loads first, its records written last):
+// the nearest node x_n from the scan's key, or the virtual root (q_g, T);
+// x_new; the [0, H] check.  Writes the worker's status (TRAPPED / SKIPPED
+// until the insert decides), new index (-1), edge flag, parent and, when the
+// extension is to be checked, x_n, x_new, the cost and root time of x_new.
+// Returns whether the extension edge (x_n, x_new) is to be checked, with both
+// endpoints in xn / xnew.
+__device__ __forceinline__ bool steer_worker(const SteerArgs &a, int64_t w, float (&xn)[kMaxDof + 1],
+                                             float (&xnew)[kMaxDof + 1]) {
     const SceneDev &sc = a.sc;
     const int d = sc.d, W = d + 1;
     const Work &k = a.w;
@@ -561,7 +566,7 @@ __global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av
     const int32_t g = a.s.grp[w];
     const unsigned long long key = k.nn_key[w];
     const float Tw = a.s.T[w];
-    float xr[kMaxDof + 1], xn[kMaxDof + 1], xnew[kMaxDof + 1];
+    float xr[kMaxDof + 1];
 #pragma unroll
     for (int j = 0; j < kMaxDof; ++j) xr[j] = j < d ? a.s.qr[(int64_t)j * a.B + w] : 0.f;
     xr[d] = a.s.tr[w];
@@ -628,13 +633,59 @@ __global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av
     k.new_idx[w] = -1;
     k.edge_valid[w] = ok ? 1 : 0;
     k.parent[w] = ok ? idx : -1;
-    if (!ok) return;
+    if (!ok) return false;
     for (int j = 0; j <= d; ++j) {
         k.xn[w * W + j] = xn[j];
         k.xnew[w * W + j] = xnew[j];
     }
     k.cost_new[w] = cost0 + step;
     k.rootT_new[w] = root0;
+    return true;
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av) {
+    const SteerArgs &a = MULTI ? av[blockIdx.y] : a0;
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.B) return;
+    float xn[kMaxDof + 1], xnew[kMaxDof + 1];
+    (void)steer_worker(a, w, xn, xnew);
+}
+
+// Steering and the extension edge check in one launch (flattened path of
+// short edges): each block steers its edges' workers itself (a3) and checks
+// the resulting edges (a4), with no round trip through a separate launch.
+template <int KIND, int OT, int OBS>
+__device__ __forceinline__ void steer_flat_body(const SteerArgs &sa, const EdgeArgs &ea, float4 *lds, int bx) {
+    const int d = sa.sc.d;
+    edge_flat_body<KIND, OT, OBS>(ea, lds, bx, [&](int64_t e, float (&A)[kMaxDof + 1], float (&B)[kMaxDof + 1]) {
+        float xn[kMaxDof + 1], xnew[kMaxDof + 1];
+        if (!steer_worker(sa, e, xn, xnew)) return false;
+        // both endpoints, earlier time first
+        const bool sw = xn[d] > xnew[d];
+#pragma unroll
+        for (int j = 0; j <= kMaxDof; ++j) {
+            A[j] = j <= d ? (sw ? xnew[j] : xn[j]) : 0.f;
+            B[j] = j <= d ? (sw ? xn[j] : xnew[j]) : 0.f;
+        }
+        return true;
+    });
+}
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(64 * kFlatWaves) void k_steer_flat(SteerArgs sa, EdgeArgs ea) {
+    extern __shared__ float4 lds[];
+    steer_flat_body<KIND, OT, OBS>(sa, ea, lds, blockIdx.x);
+}
+
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(64 * kFlatWaves) void k_steer_flat_multi(const SteerArgs *sv, const EdgeArgs *ev,
+                                                                     const int32_t *members) {
+    extern __shared__ float4 lds[];
+    const int m = members[blockIdx.y];
+    const EdgeArgs &ea = ev[m];
+    if ((int64_t)blockIdx.x * kFlatGroups * ea.flat >= ea.E) return;
+    steer_flat_body<KIND, OT, OBS>(sv[m], ea, lds, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1193,6 +1244,28 @@ static int ot_for(int O_pad) {
 }
 
 template <class F>
+static void dispatch_scene2(const SceneDev &sc, F &&f);
+
+// The edge-check kernels' instance for a scene: as dispatch_scene2, with an
+// arm that has static geometry as kDHStatic.
+template <class F>
+static void dispatch_scene_edges(const SceneDev &sc, F &&f) {
+    if (sc.kind != kTranslate && sc.stat) {
+        auto by_ot = [&](auto obs) {
+            switch (sc.ot) {
+                case 4: f(IC<kDHStatic>{}, IC<4>{}, obs); break;
+                case 8: f(IC<kDHStatic>{}, IC<8>{}, obs); break;
+                default: f(IC<kDHStatic>{}, IC<16>{}, obs); break;
+            }
+        };
+        if (sc.obs_mode == kObsShared) by_ot(IC<kObsShared>{});
+        else by_ot(IC<kObsGeneric>{});
+        return;
+    }
+    dispatch_scene2(sc, f);
+}
+
+template <class F>
 static void dispatch_scene2(const SceneDev &sc, F &&f) {
     auto by_ot = [&](auto kind, auto obs) {
         switch (sc.ot) {
@@ -1471,11 +1544,24 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     else
         k_scan<kScanConfig, false><<<dim3(a.mt_nn, a.scan_nn.nch), kTileQ, 0, s>>>(a.scan_nn, nullptr, nullptr);
     ST_HIP(hipGetLastError());
-    prof_mark(p, kStSteer, s);
-    k_steer<false><<<blocks, 256, 0, s>>>(a.steer, nullptr);
-    ST_HIP(hipGetLastError());
-    prof_mark(p, kStEdge, s);
-    ST_HIP(launch_edge_args(a.edge_ext, s));
+    if (a.edge_ext.flat) {
+        // steering (a3) inside the extension check's launch (a4); the stage
+        // timing counts the launch as the edge check
+        prof_mark(p, kStEdge, s);
+        const EdgeArgs &ea = a.edge_ext;
+        dispatch_scene_edges(p->sc, [&](auto kind, auto ot, auto obs) {
+            k_steer_flat<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+                <<<dim3(flat_blocks(ea.E, ea.flat)), dim3(64 * kFlatWaves), scene_lds_bytes(p->sc), s>>>(a.steer,
+                                                                                                          ea);
+        });
+        ST_HIP(hipGetLastError());
+    } else {
+        prof_mark(p, kStSteer, s);
+        k_steer<false><<<blocks, 256, 0, s>>>(a.steer, nullptr);
+        ST_HIP(hipGetLastError());
+        prof_mark(p, kStEdge, s);
+        ST_HIP(launch_edge_args(a.edge_ext, s));
+    }
     prof_mark(p, kStInsert, s);
     k_insert<false><<<p->tree.n_pools, 1024, 0, s>>>(a.insert, nullptr);
     ST_HIP(hipGetLastError());
@@ -1518,12 +1604,18 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     if (L.n_rr > 0)
         k_scan<kScanConfig, true>
             <<<dim3(L.mt_nn, L.nch, L.n_rr), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.rr_members);
-    k_steer<true><<<dim3(L.nb_worker, L.P), 256, 0, s>>>(SteerArgs{}, L.steer);
-    ST_HIP(hipGetLastError());
     if (L.ext_flat) {
-        for (const BatchClass &c : L.classes)
-            ST_HIP(launch_edge_flat_multi(c.key, L.edge_ext, c.members, c.n, c.nb_flat, c.lds, s));
+        // steering inside the flattened extension check, per scene class
+        for (const BatchClass &c : L.classes) {
+            dispatch_scene_edges(c.key, [&](auto kind, auto ot, auto obs) {
+                k_steer_flat_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+                    <<<dim3(c.nb_flat, c.n), dim3(64 * kFlatWaves), c.lds, s>>>(L.steer, L.edge_ext, c.members);
+            });
+            ST_HIP(hipGetLastError());
+        }
     } else {
+        k_steer<true><<<dim3(L.nb_worker, L.P), 256, 0, s>>>(SteerArgs{}, L.steer);
+        ST_HIP(hipGetLastError());
         ST_HIP(launch_edge_plan_multi(L.edge_ext, L.P, L.nb_edge, s));
         for (const BatchClass &c : L.classes)
             ST_HIP(launch_edge_items_multi(c.key, c.split_ext, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));

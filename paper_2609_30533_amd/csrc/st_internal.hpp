@@ -227,10 +227,6 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
                    const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
                    unsigned long long *work, int min_item_blocks, int split_shift);
 hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s);
-// The flattened path: blocks for E edges, and its many-problem launch.
-int flat_blocks(int64_t E, int edges_per_block);
-hipError_t launch_edge_flat_multi(const SceneDev &cls, const EdgeArgs *d_args, const int32_t *d_members,
-                                  int n_members, int max_blocks, size_t lds, hipStream_t s);
 // The same pipeline for P problems at once (records in device memory); the
 // item kernel runs once per scene class over its member records.
 hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);

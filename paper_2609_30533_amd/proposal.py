@@ -174,17 +174,25 @@ class Proposal:
         return z
 
 
-def load_pairs(path):
-    """(problem, path) pairs saved by --save-paths: each problem is drawn
-    again from its seed (the same accepted start and goal)."""
-    z = np.load(path, allow_pickle=False)
+def load_pairs(path, log=print):
+    """(problem, path) pairs saved by --save-paths.  A problem is its seed's
+    scene (obstacles do not depend on the start/goal draw) with the start and
+    goal its path begins and ends at."""
+    with np.load(path, allow_pickle=False) as z:
+        seeds, lengths, states = z["seeds"], z["lengths"], z["states"]
     out, off = [], 0
-    for seed, n in zip(z["seeds"], z["lengths"]):
-        st = z["states"][off:off + int(n)]
+    for i, (seed, n) in enumerate(zip(seeds, lengths)):
+        st = states[off:off + int(n)]
         off += int(n)
-        p = harvest_problem(int(seed))
-        if p is not None:
-            out.append((p, {"states": st}))
+        p = scenes.arm6(int(seed))
+        p.q_start = scenes.f32(st[0, :p.d])
+        p.q_goal = scenes.f32(st[-1, :p.d])
+        p.params.batch = 512
+        p.params.cap_fwd = 1 << 16
+        p.params.cap_bwd = 1 << 13
+        out.append((p, {"states": st}))
+        if (i + 1) % 4000 == 0:
+            log("[load] %d earlier paths" % (i + 1))
     return out
 
 
@@ -211,7 +219,7 @@ def main(argv=None):
         print(msg, flush=True)
 
     t0 = time.time()
-    earlier = load_pairs(a.with_paths) if a.with_paths else []
+    earlier = load_pairs(a.with_paths, log=log) if a.with_paths else []
     pairs = harvest(max(a.paths - len(earlier), 0), a.per_batch, a.plan_ms, seed0=a.seed0, log=log,
                     time_limit_s=a.harvest_s)
     if a.save_paths:

@@ -225,10 +225,12 @@ PLAN_CASES = [
     ("disc2d-rr-0", lambda: _small(scenes.disc2d(0, params=scenes.Params(variant=1, n_groups=8)), 512), 60, True),
     ("disc2d-rr-2", lambda: _small(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 512), 60, True),
     ("arm6-ir-2", lambda: _small(scenes.arm6(2), 1024, groups=8), 200, True),
-    ("arm7-rr-1", lambda: _small(scenes.arm7rr(1, n_obs=8), 1024, groups=16), 300, False),
-    ("arm7-rr-3", lambda: _small(scenes.arm7rr(3, n_obs=8), 1024, groups=16), 300, False),
-    ("arm6-static-ir-7", lambda: _small(scenes.arm6static(7), 1024, groups=8), 600, False),
-    ("arm6-static-ir-11", lambda: _small(scenes.arm6static(11), 1024, groups=8), 600, False),
+    # start and goal redrawn until the library accepts them (the attempt index
+    # found by that redraw), pools large enough for the iterations
+    ("arm7-rr-5", lambda: _small(scenes.arm7rr(5, n_obs=8, attempt=1), 1024, 1 << 16, 1 << 13, 16), 400, True),
+    ("arm7-rr-8", lambda: _small(scenes.arm7rr(8, n_obs=8, attempt=3), 1024, 1 << 16, 1 << 13, 16), 400, True),
+    ("arm6-static-ir-14", lambda: _small(scenes.arm6static(14, attempt=42), 1024, 1 << 16, 1 << 13, 8), 600, True),
+    ("arm6-static-ir-24", lambda: _small(scenes.arm6static(24, attempt=9), 1024, 1 << 16, 1 << 13, 8), 600, True),
 ]
 
 
