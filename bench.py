@@ -33,7 +33,8 @@ PEAK_BF16_TFLOPS = 2500.0     # MI355X published dense BF16 matrix-core peak
 PEAK_HBM_GBS = 8000.0
 # Sources of the edge-check kernels: a traffic figure measured with rocprofv3
 # counters is reported only while these are unchanged since the measurement.
-EDGE_KERNEL_SOURCES = ("paper_2609_30533_amd/csrc/collide.hip", "paper_2609_30533_amd/csrc/st_device.hpp")
+EDGE_KERNEL_SOURCES = ("paper_2609_30533_amd/csrc/collide.hip", "paper_2609_30533_amd/csrc/edge_flat.hpp",
+                       "paper_2609_30533_amd/csrc/extend.hip", "paper_2609_30533_amd/csrc/st_device.hpp")
 TRAFFIC_PROFILE = "profiles/traffic_arm6_single.md"
 
 
@@ -604,7 +605,8 @@ def report(args, seed, prob, gp, m, ttfs, batched, cpu, configs):
                      "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-scaled)",
                      "traffic_source": traffic_src,
-                     "kernel": "k_check_edges (extension + bridge launches)",
+                     "kernel": "edge check: extension launch k_steer_flat (steering fused with the check), "
+                               "bridge launch k_edge_plan + k_edge_items",
                      "flops_per_state": W, "states": states, "launches": launches,
                      "avg_launch_ms": ms_edge / max(launches, 1),
                      "timing": "HIP events on the launch stream around each edge-check launch, %d iterations "
