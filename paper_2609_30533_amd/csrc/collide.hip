@@ -518,6 +518,17 @@ hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_edge_items(const EdgeArgs &a, hipStream_t s) {
+    if (a.E <= 0) return hipSuccess;
+    if (a.E > a.eb.cap) return hipErrorInvalidValue;
+    const size_t lds = scene_lds_bytes(a.sc);
+    dispatch_split(a.sc, a.split_shift, [&](auto kind, auto ot, auto obs, auto split) {
+        k_edge_items<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, decltype(split)::value>
+            <<<dim3(a.nb_items), dim3(256), lds, s>>>(a);
+    });
+    return hipGetLastError();
+}
+
 hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s) {
     k_edge_plan_multi<<<dim3(max_nb_edge, P), 256, 0, s>>>(d_args);
     return hipGetLastError();

@@ -359,6 +359,7 @@ __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) 
             off += cnt[s];
         }
         a.n_tiles[0] = t;
+        a.n_tiles[1] = off;  // queries over all sets
     }
     __syncthreads();
     if (one_pass) {
@@ -903,6 +904,146 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
     k.br_valid[w] = 1;
     k.Up[w] = up;
     k.Cp[w] = cp + sqrtf(D2) + cb;
+}
+
+// Bridge selection's merge and the first states of the bridge edge in one
+// launch, one wave per advanced worker, given densely (wave i takes the i-th
+// worker of the bridge query order, so the waves that check are packed into
+// the first blocks and no SIMD holds more than one of them): the wave merges
+// its worker's per-slice candidates as k_bridge_merge does, then checks
+// states 0 .. 63 of the chosen bridge edge (lane j takes state j, the FIRST
+// rule over the wave), which decides every bridge that collides there or has
+// at most 64 states.  The rest (no hit among 64 or more states) append their
+// work items to the rank lists for the item kernel, which checks them whole.
+// Wave i also writes the empty bridge of worker i when that worker did not
+// advance.  The per-edge records (state count, least hit) are the plan
+// step's; the finish step runs in the publish kernel.
+template <int KIND, int OT, int OBS>
+__global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a, EdgeArgs ea) {
+    extern __shared__ float4 lds[];
+    const int lane = threadIdx.x & 63;
+    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const Work &k = a.w;
+    const SceneDev &sc = ea.sc;
+    const EdgeBufs &eb = ea.eb;
+    const int d = a.tree.d, W = d + 1;
+    if (i < a.B && lane == 0 && k.status[i] != ST_STATUS_ADVANCED) {
+        k.bridge[i] = -1;
+        k.br_valid[i] = 0;
+        k.Up[i] = INFINITY;
+        k.Cp[i] = INFINITY;
+        eb.n[i] = -1;
+    }
+    const int64_t nsel = *a.n_sel;
+    // a block past the advanced workers has nothing more to do (whole block)
+    if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= nsel) return;
+    const bool in = i < nsel;
+    const int64_t w = in ? a.order[i] : 0;
+    unsigned long long bk = kNoKey;
+    uint32_t bi = 0xffffffffu;
+    if (in) {
+        for (int y = lane; y < a.nch; y += 64) {
+            const int32_t ii = k.br_idx[(int64_t)w * a.nch + y];
+            if (ii < 0) continue;
+            const unsigned long long kk = k.br_key[(int64_t)w * a.nch + y];
+            if (kk < bk || (kk == bk && (uint32_t)ii < bi)) {
+                bk = kk;
+                bi = (uint32_t)ii;
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ok = __shfl_xor(bk, o, 64);
+        const uint32_t oi = __shfl_xor(bi, o, 64);
+        if (ok < bk || (ok == bk && oi < bi)) {
+            bk = ok;
+            bi = oi;
+        }
+    }
+    const bool has = in && bi != 0xffffffffu;  // the same on every lane of the wave
+    // the bridge's rows in flight while the block stages the scene
+    float y[kMaxDof + 1], xn[kMaxDof + 1];
+    float up = 0.f, cp = 0.f, cb = 0.f;
+    if (has) {
+#pragma unroll
+        for (int j = 0; j <= kMaxDof; ++j) {
+            y[j] = j <= d ? a.tree.x[(int64_t)j * a.tree.total + bi] : 0.f;
+            xn[j] = j <= d ? k.xnew[w * W + j] : 0.f;
+        }
+        up = a.dir[w] == 0 ? a.tree.rootT[bi] : k.rootT_new[w];
+        cp = k.cost_new[w];
+        cb = a.tree.cost[bi];
+    }
+    stage_obstacles(sc, lds);
+    if (!in) return;  // whole waves, after the block's barrier
+    if (!has) {
+        if (lane == 0) {
+            k.bridge[w] = -1;
+            k.br_valid[w] = 0;
+            k.Up[w] = INFINITY;
+            k.Cp[w] = INFINITY;
+            eb.n[w] = -1;
+        }
+        return;
+    }
+    float D2 = 0.f;
+#pragma unroll
+    for (int j = 0; j < kMaxDof; ++j) {
+        if (j < d) {
+            const float e = y[j] - xn[j];
+            D2 = fmaf(e, e, D2);
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j <= kMaxDof; ++j)
+            if (j <= d) k.xb[w * W + j] = y[j];
+        k.bridge[w] = (int32_t)bi;
+        k.br_valid[w] = 1;
+        k.Up[w] = up;
+        k.Cp[w] = cp + sqrtf(D2) + cb;
+    }
+    // the edge (x_new, y), earlier time first, and its state count
+    float A[kMaxDof + 1], B[kMaxDof + 1];
+    const bool sw = xn[d] > y[d];
+#pragma unroll
+    for (int j = 0; j <= kMaxDof; ++j) {
+        A[j] = sw ? y[j] : xn[j];
+        B[j] = sw ? xn[j] : y[j];
+    }
+    const int32_t n = edge_states(A, B, d, sc.v_d, sc.h_d);
+    const bool act = lane <= n;
+    float q[kMaxDof];
+    float t = 0.f;
+    if (act && lane == n) {
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) q[j] = j < d ? B[j] : 0.f;
+        t = B[d];
+    } else if (act) {
+        const float sj = (float)lane * (1.0f / (float)n);
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) q[j] = j < d ? fmaf(sj, B[j] - A[j], A[j]) : 0.f;
+        t = fmaf(sj, B[d] - A[d], A[d]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < kMaxDof; ++j) q[j] = 0.f;
+    }
+    const bool hit = state_hits<KIND, OT, OBS, true>(sc, lds, q, t, act, ~0ull, (1ull << lane) - 1ull);
+    const uint64_t hm = __ballot(hit && act);
+    if (lane == 0) {
+        eb.n[w] = n;
+        eb.hit[w] = hm ? (int32_t)__builtin_ctzll(hm) : kNoHit;
+    }
+    if (hm || n < 64) return;  // decided
+    // undecided: the whole edge goes to the item kernel (L states per chunk,
+    // up to mmax items), one rank-list append per item
+    const int L = 1 << (ea.lpe_shift - ea.split_shift);
+    const int64_t c = ((int64_t)n + L) / L;
+    const int m = (int)(c < eb.mmax ? c : eb.mmax);
+    if (lane < m) {
+        const int slot = atomicAdd(&eb.cnt[lane * kCntStride], 1);
+        eb.items[(int64_t)lane * eb.cap + slot] = make_int2((int)w, lane);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1501,6 +1642,8 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ba.nch = nch_br;
     ba.dir = in.dir;
     ba.w = w;
+    ba.order = w.order;
+    ba.n_sel = w.n_tiles + 1;
     a.edge_br = edge_args(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true),
                           p->d_plan->work + 2, min_item_blocks, split_for(p->split_br, launch_edges));
     a.edge_br.skip_finish = 1;  // k_publish reads the bridge hits itself
@@ -1570,10 +1713,16 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     ST_HIP(hipGetLastError());
     k_scan<kScanBridge, false><<<dim3(a.mt_br, a.scan_br.nch), kTileQ, 0, s>>>(a.scan_br, nullptr, nullptr);
     ST_HIP(hipGetLastError());
-    k_bridge_merge<false><<<(int)((B * 64 + 255) / 256), 256, 0, s>>>(a.merge, nullptr);
-    ST_HIP(hipGetLastError());
+    // the merge and the first 64 states of every bridge edge in one launch
+    // (its stage timing counts it as the bridge check), then the item kernel
+    // for the undecided rest
     prof_mark(p, kStBridgeEdge, s);
-    ST_HIP(launch_edge_args(a.edge_br, s));
+    dispatch_scene_edges(p->sc, [&](auto kind, auto ot, auto obs) {
+        k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
+            <<<(int)((B * 64 + 255) / 256), 256, scene_lds_bytes(p->sc), s>>>(a.merge, a.edge_br);
+    });
+    ST_HIP(hipGetLastError());
+    ST_HIP(launch_edge_items(a.edge_br, s));
     prof_mark(p, kStPublish, s);
     k_publish<false><<<1, 1024, 0, s>>>(a.publish, nullptr, a.roots, nullptr);
     ST_HIP(hipGetLastError());

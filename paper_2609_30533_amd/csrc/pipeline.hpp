@@ -81,6 +81,10 @@ struct BridgeArgs {
     int32_t nch;
     const int8_t *dir;
     Work w;
+    // the advanced workers (bridge queries) in bucket order and their number
+    // (the bridge check gives one wave to each, densely)
+    const int32_t *order;
+    const int32_t *n_sel;
 };
 
 struct PublishArgs {

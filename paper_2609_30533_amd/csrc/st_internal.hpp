@@ -227,6 +227,9 @@ EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const floa
                    const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
                    unsigned long long *work, int min_item_blocks, int split_shift);
 hipError_t launch_edge_args(const EdgeArgs &a, hipStream_t s);
+// The item kernel alone, for edges whose records (state count, least hit)
+// and work items another kernel has written (the bridge check).
+hipError_t launch_edge_items(const EdgeArgs &a, hipStream_t s);
 // The same pipeline for P problems at once (records in device memory); the
 // item kernel runs once per scene class over its member records.
 hipError_t launch_edge_plan_multi(const EdgeArgs *d_args, int P, int max_nb_edge, hipStream_t s);
