@@ -115,7 +115,6 @@ static int batch_build(st_batch *b) {
     int64_t all_edges = 0;
     for (st_problem *p : b->mem) all_edges += p->prm.batch;
     std::vector<SampleArgs> smp(P);
-    std::vector<PrepArgs> prep_nn(P), prep_br(P);
     std::vector<ScanArgs> scan_nn(P), scan_br(P);
     std::vector<SteerArgs> steer(P);
     std::vector<EdgeArgs> edge_ext(P), edge_br(P);
@@ -131,11 +130,9 @@ static int batch_build(st_batch *b) {
         st_problem *p = b->mem[m];
         const int64_t B = p->prm.batch;
         const st_samples s = work_samples_of(p);
-        smp[m] = make_sample_args(p, -1, B, s);
+        smp[m] = make_sample_args(p, -1, B, s, true);
         IterArgs a;
         make_iter_args(p, B, s, nullptr, nch, nch, min_items, all_edges, a);
-        prep_nn[m] = a.prep_nn;
-        prep_br[m] = a.prep_br;
         scan_nn[m] = a.scan_nn;
         scan_br[m] = a.scan_br;
         steer[m] = a.steer;
@@ -162,8 +159,6 @@ static int batch_build(st_batch *b) {
         b->saved_bufs.insert(b->saved_bufs.end(), sb.begin(), sb.end());
     }
     ST_HIP(upload(b->owned, smp, &L.sample));
-    ST_HIP(upload(b->owned, prep_nn, &L.prep_nn));
-    ST_HIP(upload(b->owned, prep_br, &L.prep_br));
     ST_HIP(upload(b->owned, scan_nn, &L.scan_nn));
     ST_HIP(upload(b->owned, scan_br, &L.scan_br));
     ST_HIP(upload(b->owned, steer, &L.steer));

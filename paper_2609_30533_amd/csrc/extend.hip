@@ -77,6 +77,26 @@ __device__ double ir_root_time(const WindowsDev &w, const double *wlo, const dou
     return I0 + unit24d(u[3]) * (I1 - I0);
 }
 
+// Adds `amount` lanes' worth to bucket[set] with one atomic per distinct set
+// in the wave; returns each lane's position among the lanes of its set (in
+// lane order) plus the bucket's previous value.  Every lane must call it.
+__device__ __forceinline__ int wave_bucket_add(int *bucket, int set) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(set >= 0);
+    int pos = -1;
+    while (pending) {
+        const int leader = __builtin_ctzll(pending);
+        const int ls = __shfl(set, leader, 64);
+        const uint64_t same = __ballot(set == ls) & pending;
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&bucket[ls], __popcll(same));
+        base = __shfl(base, leader, 64);
+        if (set == ls) pos = base + __popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    return pos;
+}
+
 // MULTI: many problems per launch; blockIdx.y picks the problem's record
 // (through the member list of its scene class) and blocks past the problem's
 // own grid leave at once.  The same convention holds for every kernel below.
@@ -219,6 +239,38 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
             if (dir == 1 && (!(pl->minRootT[g] < pl->U) || unit24f(u[12]) <= a.p_new)) flags |= ST_FLAG_USE_NEW;
         }
     }
+    if (a.bcnt) {
+        // the worker's nearest-node set (the forward tree, or its backward
+        // group or slot; a new interval root has none: its root is the node),
+        // its place in that set's bucket, its empty key, and the snapshot
+        // every worker of this batch sees (counts and U before any insert)
+        // (places within the block from LDS counters, then one global atomic
+        // per set and block)
+        __shared__ int s_bcnt[kMaxPools], s_bbase[kMaxPools];
+        if ((int)threadIdx.x < a.n_pools) s_bcnt[threadIdx.x] = 0;
+        __syncthreads();
+        int set = -1;
+        if (act && part == 0 && !(flags & ST_FLAG_SKIP)) {
+            if (dir == 0) set = 0;
+            else if (g >= 0 && g < a.n_pools - 1 && !(ir && (flags & ST_FLAG_USE_NEW))) set = 1 + g;
+        }
+        const int pos = wave_bucket_add(s_bcnt, set);
+        __syncthreads();
+        if ((int)threadIdx.x < a.n_pools && s_bcnt[threadIdx.x] > 0)
+            s_bbase[threadIdx.x] = atomicAdd(&a.bcnt[threadIdx.x], s_bcnt[threadIdx.x]);
+        __syncthreads();
+        if (set >= 0) a.border[(int64_t)set * a.B + s_bbase[set] + pos] = (int32_t)w;
+        if (act && part == 0) a.keys[w] = kNoKey;
+        if (blockIdx.x == 0) {
+            PlanDev *plw = const_cast<PlanDev *>(pl);
+            const int tid = threadIdx.x;
+            if (tid < a.n_pools) plw->count_snap[tid] = pl->count[tid];
+            if (tid == 0) {
+                plw->U_snap = pl->U;
+                plw->improved = 0;
+            }
+        }
+    }
     if (!act || part != 0) return;
     a.out.dir[w] = dir;
     a.out.flags[w] = flags;
@@ -233,150 +285,61 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
 // ---------------------------------------------------------------------------
 
 
-// Adds `amount` lanes' worth to bucket[set] with one atomic per distinct set
-// in the wave; returns each lane's position among the lanes of its set (in
-// lane order) plus the bucket's previous value.  Every lane must call it.
-__device__ __forceinline__ int wave_bucket_add(int *bucket, int set) {
-    const int lane = threadIdx.x & 63;
-    uint64_t pending = __ballot(set >= 0);
-    int pos = -1;
-    while (pending) {
-        const int leader = __builtin_ctzll(pending);
-        const int ls = __shfl(set, leader, 64);
-        const uint64_t same = __ballot(set == ls) & pending;
-        int base = 0;
-        if (lane == leader) base = atomicAdd(&bucket[ls], __popcll(same));
-        base = __shfl(base, leader, 64);
-        if (set == ls) pos = base + __popcll(same & ((1ull << lane) - 1ull));
-        pending &= ~same;
-    }
-    return pos;
-}
-
+// Bucketing of caller-given samples (st_extend_batch; an internal iteration's
+// sampler does this itself): each worker's nearest-node set, its place in the
+// set's bucket, its empty key, and the snapshot of the batch.  One block; the
+// counters are overwritten.
 template <bool MULTI>
 __global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) {
     const PrepArgs &a = MULTI ? av[blockIdx.y] : a0;
-    __shared__ int cnt[kMaxPools + 2], cur[kMaxPools + 2];
+    __shared__ int cnt[kMaxPools];
     const int tid = threadIdx.x;
-    const int nsets = a.mode == 0 ? a.n_pools : 2;
-    for (int i = tid; i < nsets; i += blockDim.x) cnt[i] = 0;
-    // the snapshot every worker of this batch sees (one pool per thread: a
-    // serial copy would wait for every load in turn); loaded here, stored
-    // after the worker loads, since a load behind a store waits for it
+    for (int i = tid; i < a.n_pools; i += blockDim.x) cnt[i] = 0;
+    // the snapshot every worker of this batch sees (one pool per thread),
+    // loaded here and stored after the worker loads
     int32_t snap_count = 0;
     float snap_U = 0.f;
-    if (a.mode == 0) {
-        if (tid < a.n_pools) snap_count = a.pl->count[tid];
-        if (tid == 0) snap_U = a.pl->U;
-    }
+    if (tid < a.n_pools) snap_count = a.pl->count[tid];
+    if (tid == 0) snap_U = a.pl->U;
     __syncthreads();
     // R consecutive workers per thread and pass, all loads before the stores
     constexpr int R = 4;
-    const bool one_pass = a.B <= (int64_t)blockDim.x * R;
-    int sets[R], pos[R];
     for (int64_t base = 0; base < a.B; base += (int64_t)blockDim.x * R) {
         uint8_t f[R];
         int8_t dr[R];
         int32_t g[R];
-        int8_t stt[R];
         // unconditional loads (a worker past B reads worker B - 1 and is
         // ignored): guarded loads would each wait before the next one issues
-        if (a.mode == 0) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t w = base + (int64_t)tid * R + r;
-                const int64_t wc = w < a.B ? w : a.B - 1;
-                f[r] = a.s.flags[wc];
-                dr[r] = a.s.dir[wc];
-                g[r] = a.s.grp[wc];
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (base + (int64_t)tid * R + r >= a.B) f[r] = ST_FLAG_SKIP;
-        } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int64_t w = base + (int64_t)tid * R + r;
-                const int64_t wc = w < a.B ? w : a.B - 1;
-                stt[r] = a.status[wc];
-                dr[r] = a.dir[wc];
-            }
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                if (base + (int64_t)tid * R + r >= a.B) stt[r] = 0;
+        for (int r = 0; r < R; ++r) {
+            const int64_t w = base + (int64_t)tid * R + r;
+            const int64_t wc = w < a.B ? w : a.B - 1;
+            f[r] = a.s.flags[wc];
+            dr[r] = a.s.dir[wc];
+            g[r] = a.s.grp[wc];
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int64_t w = base + (int64_t)tid * R + r;
             int set = -1;
-            if (a.mode == 0) {
-                if (!(f[r] & ST_FLAG_SKIP)) {
-                    if (dr[r] == 0) set = 0;
-                    else if (g[r] >= 0 && g[r] < a.n_pools - 1 &&
-                             !(a.variant == ST_INTERVAL_ROOT && (f[r] & ST_FLAG_USE_NEW)))
-                        set = 1 + g[r];
-                }
-            } else {
-                // forward new nodes bridge into the backward forest (set 0), backward
-                // new nodes into the forward tree (set 1)
-                if (stt[r] == ST_STATUS_ADVANCED) set = dr[r] == 0 ? 0 : 1;
+            if (w < a.B && !(f[r] & ST_FLAG_SKIP)) {
+                if (dr[r] == 0) set = 0;
+                else if (g[r] >= 0 && g[r] < a.n_pools - 1 &&
+                         !(a.variant == ST_INTERVAL_ROOT && (f[r] & ST_FLAG_USE_NEW)))
+                    set = 1 + g[r];
             }
-            if (w < a.B) {
-                a.set_of[w] = set;
-                if (a.mode == 0) a.keys[w] = kNoKey;
-            }
-            sets[r] = w < a.B ? set : -1;
-        }
-        // positions inside the sets (kept for the single-pass case)
-#pragma unroll
-        for (int r = 0; r < R; ++r) pos[r] = wave_bucket_add(cnt, sets[r]);
-    }
-    if (a.mode == 0) {
-        if (tid < a.n_pools) a.pl->count_snap[tid] = snap_count;
-        if (tid == 0) {
-            a.pl->U_snap = snap_U;
-            a.pl->improved = 0;
+            if (w < a.B) a.keys[w] = kNoKey;
+            const int pos = wave_bucket_add(cnt, set);
+            if (set >= 0) a.border[(int64_t)set * a.B + pos] = (int32_t)w;
         }
     }
-    __syncthreads();
+    if (tid < a.n_pools) a.pl->count_snap[tid] = snap_count;
     if (tid == 0) {
-        int off = 0, t = 0;
-        for (int s = 0; s < nsets; ++s) {
-            cur[s] = off;
-            for (int k = 0; k < cnt[s]; k += kTileQ) {
-                int set_id, sigma;
-                if (a.mode == 0) {
-                    set_id = s;
-                    sigma = s == 0 ? 1 : -1;
-                } else {
-                    // a bridge from x_new in direction sigma needs sigma (t_y - t_new) > 0,
-                    // i.e. the nearest-node rule with the opposite sign
-                    set_id = s == 0 ? kSetAllBackward : 0;
-                    sigma = s == 0 ? -1 : 1;
-                }
-                a.tiles[t++] = make_int4(set_id, off + k, min(kTileQ, cnt[s] - k), sigma);
-            }
-            off += cnt[s];
-        }
-        a.n_tiles[0] = t;
-        a.n_tiles[1] = off;  // queries over all sets
+        a.pl->U_snap = snap_U;
+        a.pl->improved = 0;
     }
     __syncthreads();
-    if (one_pass) {
-        // the sets and the positions inside them are still in registers
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t w = (int64_t)tid * R + r;
-            if (sets[r] >= 0) a.order[cur[sets[r]] + pos[r]] = (int32_t)w;
-        }
-    } else {
-        for (int64_t base = 0; base < a.B; base += blockDim.x) {
-            const int64_t w = base + tid;
-            const int set = w < a.B ? a.set_of[w] : -1;
-            const int pos = wave_bucket_add(cur, set);
-            if (set >= 0) a.order[pos] = (int32_t)w;
-        }
-    }
+    if (tid < a.n_pools) a.bcnt[tid] = cnt[tid];
 }
 
 // ---------------------------------------------------------------------------
@@ -402,9 +365,43 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
     const ScanArgs &a = MULTI ? av[members[blockIdx.z]] : a0;
     if (MULTI && (int)blockIdx.y >= a.nch) return;
     const int t = blockIdx.x;
-    if (t >= a.n_tiles[0]) return;
     const int tid = threadIdx.x;
-    const int4 tile = a.tiles[t];
+    int4 tile;             // set, first query, queries, sigma
+    int64_t qrow = -1;     // bucket row of the tile's queries (-1: identity order)
+    if (a.bmode == 0) {
+        if (t >= a.n_tiles[0]) return;
+        tile = a.tiles[t];
+    } else {
+        // tile t is tile kt of bucket sb: the buckets' tiles in set order,
+        // from the counts (read together, then walked from LDS by every thread)
+        __shared__ int32_t s_bc[kMaxPools];
+        const int nsets = a.bmode == 1 ? a.tree.n_pools : 2;
+        if (tid < nsets) s_bc[tid] = a.bcnt[tid];
+        __syncthreads();
+        int acc = 0, sb = 0, kt = -1;
+        for (; sb < nsets; ++sb) {
+            const int nt = (s_bc[sb] + kTileQ - 1) / kTileQ;
+            if (t < acc + nt) {
+                kt = t - acc;
+                break;
+            }
+            acc += nt;
+        }
+        if (kt < 0) return;  // past the last tile (the same for the whole block)
+        int set_id, sg;
+        if (a.bmode == 1) {
+            set_id = sb;
+            sg = sb == 0 ? 1 : -1;
+        } else {
+            // a bridge from x_new in direction sigma needs sigma (t_y - t_new) > 0,
+            // i.e. the nearest-node rule with the opposite sign: forward new
+            // nodes into the backward forest, backward new nodes into the tree
+            set_id = sb == 0 ? kSetAllBackward : 0;
+            sg = sb == 0 ? -1 : 1;
+        }
+        tile = make_int4(set_id, kt * kTileQ, min(kTileQ, s_bc[sb] - kt * kTileQ), sg);
+        qrow = (int64_t)sb * a.bstride;
+    }
     const int set = tile.x, n = tile.z;
     const float sv = (float)tile.w * a.v;  // sigma * v
     const int d = a.tree.d;
@@ -446,7 +443,7 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
         if ((int)blockIdx.y >= nch) return;
     }
     const bool act = tid < n;
-    const int q = act ? (a.order ? a.order[tile.y + tid] : tile.y + tid) : 0;
+    const int q = act ? (qrow >= 0 ? a.border[qrow + tile.y + tid] : tile.y + tid) : 0;
     const int64_t c0 = (int64_t)blockIdx.y * total / nch, c1 = (int64_t)(blockIdx.y + 1) * total / nch;
     float qx[kMaxDof];
     float aq = 0.f;
@@ -698,6 +695,7 @@ template <bool MULTI>
 __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs *av) {
     __shared__ int wsum[32];
     __shared__ int s_total, s_last;
+    __shared__ int s_bcnt[2], s_bbase[2];  // bridge bucket places of this pass
     const InsertArgs &a = MULTI ? av[blockIdx.y] : a0;
     const int p = blockIdx.x;
     if (MULTI && p >= a.tree.n_pools) return;
@@ -711,6 +709,9 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
     const int64_t avail = pool_cap(a.tree, p) - snap;
     int64_t running = 0;
     if (tid == 0) s_last = 0;
+    if (tid < 2) s_bcnt[tid] = 0;
+    // the nearest-node buckets are consumed: empty for the next batch
+    if (p == 0 && tid < a.tree.n_pools) k.bcnt[tid] = 0;
     // R consecutive workers per thread and pass; all their loads are issued
     // before any store
     constexpr int R = 4;
@@ -785,8 +786,10 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
         }
         __syncthreads();
         int64_t off = running + wsum[wv] + incl - tot;
+        int bset[R];  // bridge bucket of an inserted worker (0 forward, 1 backward)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
+            bset[r] = -1;
             if (need[r] == 0) continue;
             const int64_t w = c0 + (int64_t)tid * R + r;
             if (off + need[r] > avail) {
@@ -820,9 +823,26 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
                 k.new_idx[w] = (int32_t)idx;
                 k.status[w] = ST_STATUS_ADVANCED;
                 atomicMax(&s_last, (int)(off + need[r]));
+                bset[r] = dr[r] == 0 ? 0 : 1;
             }
             off += need[r];
         }
+        // the inserted workers are the bridge queries (a6): places within the
+        // block from LDS counters, then one global atomic per set and pass
+        int bpos[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) bpos[r] = wave_bucket_add(s_bcnt, bset[r]);
+        __syncthreads();
+        if (tid < 2) {
+            const int c = s_bcnt[tid];
+            s_bbase[tid] = c > 0 ? atomicAdd(&k.bcnt[kBcntBridge + tid], c) : 0;
+            s_bcnt[tid] = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (bset[r] >= 0)
+                k.border_br[(int64_t)bset[r] * a.B + s_bbase[bset[r]] + bpos[r]] = (int32_t)(c0 + (int64_t)tid * R + r);
         // collided extensions (disjoint from the inserted workers), written
         // last so that no load of this pass waits behind them
 #pragma unroll
@@ -908,7 +928,7 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
 
 // Bridge selection's merge and the first states of the bridge edge in one
 // launch, one wave per advanced worker, given densely (wave i takes the i-th
-// worker of the bridge query order, so the waves that check are packed into
+// worker of the bridge buckets, so the waves that check are packed into
 // the first blocks and no SIMD holds more than one of them): the wave merges
 // its worker's per-slice candidates as k_bridge_merge does, then checks
 // states 0 .. 63 of the chosen bridge edge (lane j takes state j, the FIRST
@@ -934,11 +954,12 @@ __global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a, EdgeArgs ea)
         k.Cp[i] = INFINITY;
         eb.n[i] = -1;
     }
-    const int64_t nsel = *a.n_sel;
+    const int32_t nb0 = k.bcnt[kBcntBridge], nb1 = k.bcnt[kBcntBridge + 1];
+    const int64_t nsel = (int64_t)nb0 + nb1;
     // a block past the advanced workers has nothing more to do (whole block)
     if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= nsel) return;
     const bool in = i < nsel;
-    const int64_t w = in ? a.order[i] : 0;
+    const int64_t w = in ? (i < nb0 ? k.border_br[i] : k.border_br[a.B + (i - nb0)]) : 0;
     unsigned long long bk = kNoKey;
     uint32_t bi = 0xffffffffu;
     if (in) {
@@ -1235,8 +1256,10 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
         atomicAdd(&a.work_br[0], edges);
         atomicAdd(&a.work_br[1], states);
     }
-    // the rank lists of the edge pipeline are consumed: empty for the next launch
+    // the rank lists of the edge pipeline and the bridge buckets are consumed:
+    // empty for the next launch
     if (tid < a.eb.mmax) a.eb.cnt[tid * kCntStride] = 0;
+    if (tid < 2) k.bcnt[kBcntBridge + tid] = 0;
     // optional caller outputs (a candidate that is not a free bridge of an
     // advanced worker reports U = C = infinity)
     const st_extend_out &o = a.out;
@@ -1430,7 +1453,7 @@ static hipError_t dalloc(T **p, size_t n) {
 
 void work_free(st_problem *p) {
     Work &w = p->work;
-    void *bufs[] = {w.dir, w.flags, w.grp, w.T, w.qr, w.tr, w.nn_key, w.set_of, w.order, w.tiles, w.n_tiles,
+    void *bufs[] = {w.dir, w.flags, w.grp, w.T, w.qr, w.tr, w.nn_key, w.tiles, w.n_tiles, w.bcnt, w.border_nn, w.border_br,
                     w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit, w.status, w.parent, w.new_idx, w.cost_new,
                     w.rootT_new, w.br_key, w.br_idx, w.bridge, w.xb, w.br_valid, w.br_free, w.Up, w.Cp};
     for (void *b : bufs)
@@ -1457,8 +1480,9 @@ int work_reserve(st_problem *p, int64_t B) {
     ST_HIP(dalloc(&w.qr, (size_t)B * p->d));
     ST_HIP(dalloc(&w.tr, B));
     ST_HIP(dalloc(&w.nn_key, B));
-    ST_HIP(dalloc(&w.set_of, B));
-    ST_HIP(dalloc(&w.order, B));
+    ST_HIP(dalloc(&w.bcnt, kBcntSize));
+    ST_HIP(dalloc(&w.border_nn, (size_t)p->tree.n_pools * B));
+    ST_HIP(dalloc(&w.border_br, (size_t)2 * B));
     ST_HIP(dalloc(&w.tiles, (size_t)mt * 4));
     ST_HIP(dalloc(&w.n_tiles, 4));
     ST_HIP(dalloc(&w.xn, (size_t)B * W));
@@ -1479,6 +1503,7 @@ int work_reserve(st_problem *p, int64_t B) {
     ST_HIP(dalloc(&w.br_free, B));
     ST_HIP(dalloc(&w.Up, B));
     ST_HIP(dalloc(&w.Cp, B));
+    ST_HIP(hipMemset(w.bcnt, 0, kBcntSize * sizeof(int32_t)));
     ST_HIP(hipMemset(w.edge_free, 0, B));
     ST_HIP(hipMemset(w.br_free, 0, B));
     return ST_OK;
@@ -1507,7 +1532,7 @@ void prof_mark(st_problem *p, int stage, hipStream_t s) {
     p->prof_used++;
 }
 
-SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out) {
+SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out, bool bucket) {
     SampleArgs a;
     memset(&a, 0, sizeof a);
     a.sc = p->sc;
@@ -1526,6 +1551,10 @@ SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const 
     a.out = out;
     a.nb = (int)((B * (p->sc.kind == kDH ? sample_lanes<kDH>() : 1) + 255) / 256);
     (void)sample_lds_bytes(p, &a.nw_lds);
+    a.n_pools = p->tree.n_pools;
+    a.bcnt = bucket ? p->work.bcnt : nullptr;
+    a.border = bucket ? p->work.border_nn : nullptr;
+    a.keys = bucket ? p->work.nn_key : nullptr;
     return a;
 }
 
@@ -1538,9 +1567,9 @@ size_t sample_lds_bytes(const st_problem *p, int32_t *nw_lds) {
     return scene + (fit ? (size_t)nw * 3 * sizeof(double) : 0);
 }
 
-int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s) {
+int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s, bool bucket) {
     prof_mark(p, kStSample, s);
-    const SampleArgs a = make_sample_args(p, iter, B, out);
+    const SampleArgs a = make_sample_args(p, iter, B, out, bucket);
     const size_t lds = sample_lds_bytes(p, nullptr);
     dispatch_scene2(p->sc, [&](auto kind, auto ot, auto obs) {
         k_sample<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, false>
@@ -1566,12 +1595,9 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     pa.d = d;
     pa.B = B;
     pa.s = in;
-    pa.set_of = w.set_of;
-    pa.order = w.order;
-    pa.tiles = (int4 *)w.tiles;
-    pa.n_tiles = w.n_tiles;
+    pa.bcnt = w.bcnt;
+    pa.border = w.border_nn;
     pa.keys = w.nn_key;
-    pa.mode = 0;
     a.mt_nn = max_tiles(B, np);
     ScanArgs &sa = a.scan_nn;
     memset(&sa, 0, sizeof sa);
@@ -1586,9 +1612,10 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     sa.sj = B;
     sa.qt = in.tr;
     sa.st = 1;
-    sa.order = w.order;
-    sa.tiles = (const int4 *)w.tiles;
-    sa.n_tiles = w.n_tiles;
+    sa.bmode = 1;
+    sa.bcnt = w.bcnt;
+    sa.border = w.border_nn;
+    sa.bstride = B;
     sa.keys = w.nn_key;
     sa.nch = nch_nn;
     // steering (a3)
@@ -1618,10 +1645,6 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ia.s = in;
     ia.w = w;
     // bridges (a6)
-    a.prep_br = pa;
-    a.prep_br.mode = 1;
-    a.prep_br.status = w.status;
-    a.prep_br.dir = in.dir;
     a.mt_br = max_tiles(B, 2);
     ScanArgs &sb = a.scan_br;
     sb = sa;
@@ -1631,6 +1654,9 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     sb.sj = 1;
     sb.qt = w.xnew + d;
     sb.st = d + 1;
+    sb.bmode = 2;
+    sb.bcnt = w.bcnt + kBcntBridge;
+    sb.border = w.border_br;
     sb.keys = nullptr;
     sb.pkey = w.br_key;
     sb.pidx = w.br_idx;
@@ -1642,8 +1668,6 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ba.nch = nch_br;
     ba.dir = in.dir;
     ba.w = w;
-    ba.order = w.order;
-    ba.n_sel = w.n_tiles + 1;
     a.edge_br = edge_args(p->sc, p->ebufs, B, w.xnew, w.xb, w.br_valid, w.br_free, w.first_hit, edge_shift(p, true),
                           p->d_plan->work + 2, min_item_blocks, split_for(p->split_br, launch_edges));
     a.edge_br.skip_finish = 1;  // k_publish reads the bridge hits itself
@@ -1668,7 +1692,8 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     ra.no_recycling = p->prm.no_recycling;
 }
 
-int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s) {
+int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s,
+                 bool bucketed) {
     int rc = work_reserve(p, B);
     if (rc != ST_OK) return rc;
     if (p->ebufs.cap < B) {
@@ -1680,8 +1705,10 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
                    B, a);
     const int blocks = (int)((B + 255) / 256);
     prof_mark(p, kStNearest, s);
-    k_prep<false><<<1, 1024, 0, s>>>(a.prep_nn, nullptr);
-    ST_HIP(hipGetLastError());
+    if (!bucketed) {
+        k_prep<false><<<1, 1024, 0, s>>>(a.prep_nn, nullptr);
+        ST_HIP(hipGetLastError());
+    }
     if (p->prm.variant == ST_INTERVAL_ROOT)
         k_scan<kScanRho, false><<<dim3(a.mt_nn, a.scan_nn.nch), kTileQ, 0, s>>>(a.scan_nn, nullptr, nullptr);
     else
@@ -1709,8 +1736,6 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     k_insert<false><<<p->tree.n_pools, 1024, 0, s>>>(a.insert, nullptr);
     ST_HIP(hipGetLastError());
     prof_mark(p, kStBridgeSel, s);
-    k_prep<false><<<1, 1024, 0, s>>>(a.prep_br, nullptr);
-    ST_HIP(hipGetLastError());
     k_scan<kScanBridge, false><<<dim3(a.mt_br, a.scan_br.nch), kTileQ, 0, s>>>(a.scan_br, nullptr, nullptr);
     ST_HIP(hipGetLastError());
     // the merge and the first 64 states of every bridge edge in one launch
@@ -1747,7 +1772,6 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
         });
     }
     ST_HIP(hipGetLastError());
-    k_prep<true><<<dim3(1, L.P), 1024, 0, s>>>(PrepArgs{}, L.prep_nn);
     if (L.n_ir > 0)
         k_scan<kScanRho, true><<<dim3(L.mt_nn, L.nch, L.n_ir), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.ir_members);
     if (L.n_rr > 0)
@@ -1771,7 +1795,6 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
         ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
     }
     k_insert<true><<<dim3(L.max_pools, L.P), 1024, 0, s>>>(InsertArgs{}, L.insert);
-    k_prep<true><<<dim3(1, L.P), 1024, 0, s>>>(PrepArgs{}, L.prep_br);
     k_scan<kScanBridge, true><<<dim3(L.mt_br, L.nch, L.P), kTileQ, 0, s>>>(ScanArgs{}, L.scan_br, L.all_members);
     k_bridge_merge<true><<<dim3(L.nb_merge, L.P), 256, 0, s>>>(BridgeArgs{}, L.merge);
     ST_HIP(hipGetLastError());
@@ -1805,7 +1828,7 @@ int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64
     sa.sj = 1;
     sa.qt = xq + p->d;
     sa.st = p->d + 1;
-    sa.order = nullptr;
+    sa.bmode = 0;
     sa.tiles = (const int4 *)w.tiles;
     sa.n_tiles = w.n_tiles;
     sa.keys = w.nn_key;
@@ -1852,8 +1875,8 @@ static int capture_iterations(st_problem *p, int n, hipGraphExec_t *out) {
     ST_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = ST_OK;
     for (int i = 0; i < n && rc == ST_OK; ++i) {
-        rc = sample_batch(p, -1, B, smp, cs);
-        if (rc == ST_OK) rc = extend_batch(p, B, smp, nullptr, cs);
+        rc = sample_batch(p, -1, B, smp, cs, true);
+        if (rc == ST_OK) rc = extend_batch(p, B, smp, nullptr, cs, true);
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
@@ -1888,8 +1911,8 @@ static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
         // eager launches (stage timing records events between kernels)
         const st_samples smp = work_samples(p);
         for (int64_t i = 0; i < iters; ++i) {
-            if ((rc = sample_batch(p, -1, B, smp, s)) != ST_OK) return rc;
-            if ((rc = extend_batch(p, B, smp, nullptr, s)) != ST_OK) return rc;
+            if ((rc = sample_batch(p, -1, B, smp, s, true)) != ST_OK) return rc;
+            if ((rc = extend_batch(p, B, smp, nullptr, s, true)) != ST_OK) return rc;
             p->iter++;
         }
         return ST_OK;
@@ -2041,7 +2064,7 @@ int st_sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples *ou
         return ST_EINVAL;
     }
     if (B == 0) return ST_OK;
-    return sample_batch(p, iter, B, *out, (hipStream_t)stream);
+    return sample_batch(p, iter, B, *out, (hipStream_t)stream, false);
 }
 
 int st_extend_batch(st_problem *p, int64_t B, const st_samples *s, const st_extend_out *o, void *stream) {
@@ -2050,7 +2073,7 @@ int st_extend_batch(st_problem *p, int64_t B, const st_samples *s, const st_exte
         return ST_EINVAL;
     }
     if (B == 0) return ST_OK;
-    int rc = extend_batch(p, B, *s, o, (hipStream_t)stream);
+    int rc = extend_batch(p, B, *s, o, (hipStream_t)stream, false);
     if (rc == ST_OK) p->iter++;
     return rc;
 }

@@ -20,20 +20,21 @@ struct SampleArgs {
     st_samples out;
     int32_t nb;           // blocks (many-problem launches)
     int32_t nw_lds;       // guided windows staged in LDS after the scene (0: read from device memory)
+    // internal iterations: the sampler also buckets its workers by
+    // nearest-node set, clears their keys and takes the batch's snapshot
+    // (null bcnt: samples for a caller, no bucketing)
+    int32_t n_pools;
+    int32_t *bcnt, *border;
+    unsigned long long *keys;
 };
 
 struct PrepArgs {
     PlanDev *pl;
     int32_t variant, n_pools, d;
     int64_t B;
-    st_samples s;       // mode 0 (nearest node)
-    const int8_t *status; // mode 1 (bridges)
-    const int8_t *dir;
-    int32_t *set_of, *order;
-    int4 *tiles;
-    int32_t *n_tiles;
+    st_samples s;
+    int32_t *bcnt, *border;  // nearest-node buckets (counters overwritten)
     unsigned long long *keys;
-    int32_t mode;       // 0 nearest node, 1 bridges
 };
 
 struct ScanArgs {
@@ -44,9 +45,13 @@ struct ScanArgs {
     // query q: coordinate j at qx[q sq + j sj] (j < d), time at qt[q st]
     const float *qx, *qt;
     int64_t sq, sj, st;
-    const int32_t *order;   // query ids per tile slot (null: identity)
+    // queries per tile: bmode 0 from the tile list (identity query order);
+    // 1 nearest-node buckets (sets = pools); 2 bridge buckets (two sets)
+    int32_t bmode;
     const int4 *tiles;
     const int32_t *n_tiles;
+    const int32_t *bcnt, *border;
+    int64_t bstride;
     unsigned long long *keys;  // nearest node: per-query atomic minimum
     unsigned long long *pkey;  // bridges: [nch][pstride]
     int32_t *pidx;
@@ -72,7 +77,7 @@ struct InsertArgs {
     int32_t variant;
     int64_t B;
     st_samples s;
-    Work w;
+    Work w;  // also: clears the nearest-node bucket counters, fills the bridge buckets
 };
 
 struct BridgeArgs {
@@ -80,11 +85,7 @@ struct BridgeArgs {
     int64_t B;
     int32_t nch;
     const int8_t *dir;
-    Work w;
-    // the advanced workers (bridge queries) in bucket order and their number
-    // (the bridge check gives one wave to each, densely)
-    const int32_t *order;
-    const int32_t *n_sel;
+    Work w;  // the bridge buckets give the advanced workers (one wave each, densely)
 };
 
 struct PublishArgs {
@@ -109,7 +110,7 @@ struct RootsArgs {
 
 // Every record of one iteration of one problem.
 struct IterArgs {
-    PrepArgs prep_nn, prep_br;
+    PrepArgs prep_nn;
     ScanArgs scan_nn, scan_br;
     SteerArgs steer;
     EdgeArgs edge_ext, edge_br;
@@ -120,7 +121,9 @@ struct IterArgs {
     int mt_nn, mt_br;  // query tiles at most
 };
 
-SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out);
+// bucket: the sampler of an internal iteration (buckets its workers; the
+// extend step then runs without the separate bucketing kernel)
+SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const st_samples &out, bool bucket);
 // nch_*: node slices per scan tile; min_item_blocks: least blocks of the edge
 // item kernel; launch_edges: edges of the whole launch (for the automatic
 // lanes per state).
@@ -144,7 +147,6 @@ struct BatchClass {
 struct BatchLaunch {
     int P = 0;
     const SampleArgs *sample = nullptr;
-    const PrepArgs *prep_nn = nullptr, *prep_br = nullptr;
     const ScanArgs *scan_nn = nullptr, *scan_br = nullptr;
     const SteerArgs *steer = nullptr;
     const EdgeArgs *edge_ext = nullptr, *edge_br = nullptr;

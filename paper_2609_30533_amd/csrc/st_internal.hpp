@@ -92,6 +92,8 @@ struct WindowsDev {
 // Edge-check pipeline: hit[e] holds kNoHit until a colliding state is found;
 // the rank counters sit kCntStride ints (128 bytes) apart.
 constexpr int32_t kNoHit = 0x7fffffff;
+constexpr int kBcntBridge = 128;  // bridge bucket counters (own cache lines)
+constexpr int kBcntSize = 160;
 constexpr int kCntStride = 32;
 
 // Work buffers of the edge-check pipeline (capacity cap edges).
@@ -132,10 +134,14 @@ struct Work {
     float *T, *qr, *tr;
     // extension
     unsigned long long *nn_key;  // [B] packed (distance bits, node index)
-    int32_t *set_of;             // [B] nearest-node set (pool) or -1
-    int32_t *order;              // [B] workers grouped by set
-    int32_t *tiles;              // [3 * max_tiles]: set, first, count
+    int32_t *tiles;              // [4 * max_tiles]: set, first, count, sigma (st_nearest)
     int32_t *n_tiles;            // [2]
+    // query buckets: the workers of each node set, set s at [s][Bcap]; their
+    // counters at bcnt[s] (nearest-node sets = pools) and bcnt[kBcntBridge + s]
+    // (bridge sets: 0 forward new nodes, 1 backward new nodes)
+    int32_t *bcnt;
+    int32_t *border_nn;          // [kMaxPools][Bcap]
+    int32_t *border_br;          // [2][Bcap]
     float *xn, *xnew;            // [B][d+1]
     uint8_t *edge_valid, *edge_free;
     int32_t *first_hit;          // [B] scratch for the edge checks
@@ -246,8 +252,12 @@ void prof_mark(st_problem *p, int stage, hipStream_t s);
 // ---- nearest node and the extension pipeline --------------------------------
 int nearest_set(st_problem *p, int32_t set, int32_t metric, int32_t sigma, int64_t M, const float *xq,
                 int32_t *idx_out, float *dist_out, hipStream_t s);
-int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s);
-int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s);
+// bucket (sample_batch): the sampler also buckets its workers by nearest-node
+// set; bucketed (extend_batch): the samples were so bucketed (no separate
+// bucketing kernel).  Both are set for the planner's own iterations.
+int sample_batch(st_problem *p, int64_t iter, int64_t B, const st_samples &out, hipStream_t s, bool bucket);
+int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend_out *out, hipStream_t s,
+                 bool bucketed);
 int work_reserve(st_problem *p, int64_t B);
 void work_free(st_problem *p);
 void graphs_free(st_problem *p);
