@@ -103,7 +103,7 @@ __device__ __forceinline__ int wave_bucket_add(int *bucket, int set) {
 // Lanes per worker in the sampler: the arm's root check (q_g, T) shares the
 // spheres out among four lanes; every lane of a worker draws the same numbers.
 template <int KIND>
-constexpr int sample_lanes() { return KIND == kDH ? 4 : 1; }
+constexpr int sample_lanes() { return KIND == kTranslate ? 1 : 4; }
 
 template <int KIND, int OT, int OBS, bool MULTI>
 __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs *av, const int32_t *members) {
@@ -442,8 +442,14 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
         nch = (int)min<int64_t>(nch, max<int64_t>(want, 1));
         if ((int)blockIdx.y >= nch) return;
     }
-    const bool act = tid < n;
-    const int q = act ? (qrow >= 0 ? a.border[qrow + tile.y + tid] : tile.y + tid) : 0;
+    // lanes per query: as many as the tile's queries leave free (a power of
+    // two, at most a wave); lane `sub` of a query takes every L-th node of a
+    // round, and the query's L lanes combine their bests at the end
+    int lq_shift = 0;
+    while (lq_shift < 6 && n * (2 << lq_shift) <= kTileQ) ++lq_shift;
+    const int L = 1 << lq_shift, qs = tid >> lq_shift, sub = tid & (L - 1);
+    const bool act = qs < n;
+    const int q = act ? (qrow >= 0 ? a.border[qrow + tile.y + qs] : tile.y + qs) : 0;
     const int64_t c0 = (int64_t)blockIdx.y * total / nch, c1 = (int64_t)(blockIdx.y + 1) * total / nch;
     float qx[kMaxDof];
     float aq = 0.f;
@@ -497,7 +503,7 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
             const float4 *sx4 = reinterpret_cast<const float4 *>(&sx[0][0]);
             int kb = -1;
 #pragma unroll 8
-            for (int k = 0; k < m; ++k) {
+            for (int k = sub; k < m; k += L) {
                 const float4 lo = sx4[2 * k], hi = sx4[2 * k + 1];
                 const float xs[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
                 // every slot: those past d are 0 on both sides and add exact zeros
@@ -530,13 +536,32 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av
             if (kb >= 0) bi = sI[kb];
         }
     }
-    if (!act) return;
+    // the query's lanes combine (every lane of the wave takes part): the
+    // least key, ties to the least node index, as one lane walking all the
+    // nodes in order would keep
     if (MODE == kScanBridge) {
-        a.pkey[(int64_t)q * a.pstride + blockIdx.y] =
+        unsigned long long pk =
             bi < 0 ? kNoKey : (((unsigned long long)__float_as_uint(bestT) << 32) | __float_as_uint(best));
-        a.pidx[(int64_t)q * a.pstride + blockIdx.y] = bi;
-    } else if (bi >= 0) {
-        atomicMin(&a.keys[q], pack_key(best, bi));
+        uint32_t pi = (uint32_t)bi;
+        for (int o = 1; o < L; o <<= 1) {
+            const unsigned long long ok = __shfl_xor(pk, o, 64);
+            const uint32_t oi = __shfl_xor(pi, o, 64);
+            if (ok < pk || (ok == pk && oi < pi)) {
+                pk = ok;
+                pi = oi;
+            }
+        }
+        if (!act || sub != 0) return;
+        a.pkey[(int64_t)q * a.pstride + blockIdx.y] = pk;
+        a.pidx[(int64_t)q * a.pstride + blockIdx.y] = (int32_t)pi;
+    } else {
+        unsigned long long key = bi >= 0 ? pack_key(best, bi) : kNoKey;
+        for (int o = 1; o < L; o <<= 1) {
+            const unsigned long long ok = __shfl_xor(key, o, 64);
+            key = ok < key ? ok : key;
+        }
+        if (!act || sub != 0 || key == kNoKey) return;
+        atomicMin(&a.keys[q], key);
     }
 }
 
@@ -859,78 +884,12 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
 // ---------------------------------------------------------------------------
 
 
-template <bool MULTI>
-__global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const BridgeArgs *av) {
-    const BridgeArgs &a = MULTI ? av[blockIdx.y] : a0;
-    // one wave per worker: lane y reads slices y, y + 64, ... and keeps the best
-    const int lane = threadIdx.x & 63;
-    const int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    if (w >= a.B) return;
-    const Work &k = a.w;
-    const int d = a.tree.d, W = d + 1;
-    const bool adv = k.status[w] == ST_STATUS_ADVANCED;
-    unsigned long long bk = kNoKey;
-    uint32_t bi = 0xffffffffu;
-    if (adv) {
-        for (int y = lane; y < a.nch; y += 64) {
-            const int32_t ii = k.br_idx[(int64_t)w * a.nch + y];
-            if (ii < 0) continue;
-            const unsigned long long kk = k.br_key[(int64_t)w * a.nch + y];
-            if (kk < bk || (kk == bk && (uint32_t)ii < bi)) {
-                bk = kk;
-                bi = (uint32_t)ii;
-            }
-        }
-    }
-    // lexicographic (key, index) minimum over the wave
-    for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long ok = __shfl_xor(bk, o, 64);
-        const uint32_t oi = __shfl_xor(bi, o, 64);
-        if (ok < bk || (ok == bk && oi < bi)) {
-            bk = ok;
-            bi = oi;
-        }
-    }
-    if (lane != 0) return;
-    if (!adv || bi == 0xffffffffu) {
-        k.bridge[w] = -1;
-        k.br_valid[w] = 0;
-        k.Up[w] = INFINITY;
-        k.Cp[w] = INFINITY;
-        return;
-    }
-    // all loads first: the stores may alias them for the compiler, and a load
-    // behind a store waits for the store's completion too
-    float y[kMaxDof + 1], xn[kMaxDof + 1];
-#pragma unroll
-    for (int j = 0; j <= kMaxDof; ++j) {
-        y[j] = j <= d ? a.tree.x[(int64_t)j * a.tree.total + bi] : 0.f;
-        xn[j] = j < d ? k.xnew[w * W + j] : 0.f;
-    }
-    const float up = a.dir[w] == 0 ? a.tree.rootT[bi] : k.rootT_new[w];
-    const float cp = k.cost_new[w], cb = a.tree.cost[bi];
-    float D2 = 0.f;
-#pragma unroll
-    for (int j = 0; j < kMaxDof; ++j) {
-        if (j < d) {
-            const float e = y[j] - xn[j];
-            D2 = fmaf(e, e, D2);
-        }
-    }
-#pragma unroll
-    for (int j = 0; j <= kMaxDof; ++j)
-        if (j <= d) k.xb[w * W + j] = y[j];
-    k.bridge[w] = (int32_t)bi;
-    k.br_valid[w] = 1;
-    k.Up[w] = up;
-    k.Cp[w] = cp + sqrtf(D2) + cb;
-}
-
 // Bridge selection's merge and the first states of the bridge edge in one
 // launch, one wave per advanced worker, given densely (wave i takes the i-th
 // worker of the bridge buckets, so the waves that check are packed into
 // the first blocks and no SIMD holds more than one of them): the wave merges
-// its worker's per-slice candidates as k_bridge_merge does, then checks
+// its worker's per-slice candidates (the lexicographic (key, index) minimum
+// over the slices: arrival, then rho, then node index), then checks
 // states 0 .. 63 of the chosen bridge edge (lane j takes state j, the FIRST
 // rule over the wave), which decides every bridge that collides there or has
 // at most 64 states.  The rest (no hit among 64 or more states) append their
@@ -938,9 +897,15 @@ __global__ __launch_bounds__(256) void k_bridge_merge(BridgeArgs a0, const Bridg
 // Wave i also writes the empty bridge of worker i when that worker did not
 // advance.  The per-edge records (state count, least hit) are the plan
 // step's; the finish step runs in the publish kernel.
-template <int KIND, int OT, int OBS>
-__global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a, EdgeArgs ea) {
+template <int KIND, int OT, int OBS, bool MULTI>
+__global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a0, EdgeArgs ea0, const BridgeArgs *av,
+                                                      const EdgeArgs *ev, const int32_t *members) {
     extern __shared__ float4 lds[];
+    const int mi = MULTI ? members[blockIdx.y] : 0;
+    const BridgeArgs &a = MULTI ? av[mi] : a0;
+    const EdgeArgs &ea = MULTI ? ev[mi] : ea0;
+    // many problems per launch: blocks past this problem's own grid leave
+    if (MULTI && (int64_t)blockIdx.x * (blockDim.x >> 6) >= a.B) return;
     const int lane = threadIdx.x & 63;
     const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const Work &k = a.w;
@@ -1549,7 +1514,7 @@ SampleArgs make_sample_args(const st_problem *p, int64_t iter, int64_t B, const 
     a.t_min = p->t_min;
     a.t_max = p->t_max;
     a.out = out;
-    a.nb = (int)((B * (p->sc.kind == kDH ? sample_lanes<kDH>() : 1) + 255) / 256);
+    a.nb = (int)((B * (p->sc.kind == kTranslate ? 1 : sample_lanes<kDH>()) + 255) / 256);
     (void)sample_lds_bytes(p, &a.nw_lds);
     a.n_pools = p->tree.n_pools;
     a.bcnt = bucket ? p->work.bcnt : nullptr;
@@ -1743,8 +1708,9 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     // for the undecided rest
     prof_mark(p, kStBridgeEdge, s);
     dispatch_scene_edges(p->sc, [&](auto kind, auto ot, auto obs) {
-        k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value>
-            <<<(int)((B * 64 + 255) / 256), 256, scene_lds_bytes(p->sc), s>>>(a.merge, a.edge_br);
+        k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, false>
+            <<<(int)((B * 64 + 255) / 256), 256, scene_lds_bytes(p->sc), s>>>(a.merge, a.edge_br, nullptr, nullptr,
+                                                                             nullptr);
     });
     ST_HIP(hipGetLastError());
     ST_HIP(launch_edge_items(a.edge_br, s));
@@ -1796,9 +1762,15 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     }
     k_insert<true><<<dim3(L.max_pools, L.P), 1024, 0, s>>>(InsertArgs{}, L.insert);
     k_scan<kScanBridge, true><<<dim3(L.mt_br, L.nch, L.P), kTileQ, 0, s>>>(ScanArgs{}, L.scan_br, L.all_members);
-    k_bridge_merge<true><<<dim3(L.nb_merge, L.P), 256, 0, s>>>(BridgeArgs{}, L.merge);
-    ST_HIP(hipGetLastError());
-    ST_HIP(launch_edge_plan_multi(L.edge_br, L.P, L.nb_edge, s));
+    // the merge and the first 64 states of every bridge edge, per scene
+    // class, then the item kernel for the undecided rest
+    for (const BatchClass &c : L.classes) {
+        dispatch_scene_edges(c.key, [&](auto kind, auto ot, auto obs) {
+            k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, true>
+                <<<dim3(L.nb_merge, c.n), 256, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
+        });
+        ST_HIP(hipGetLastError());
+    }
     for (const BatchClass &c : L.classes)
         ST_HIP(launch_edge_items_multi(c.key, c.split_br, L.edge_br, c.members, c.n, c.nb_items_br, c.lds, s));
     k_publish<true><<<dim3(1, L.P), 1024, 0, s>>>(PublishArgs{}, L.publish, RootsArgs{}, L.roots);

@@ -29,6 +29,17 @@ def _small(prob, batch, cap_f=1 << 14, cap_b=1 << 11, groups=None):
     return prob
 
 
+def _c3_parked(seed):
+    """The recycling workload at its full shape (7-DOF arm, 60 spheres, 32
+    moving spheres x 16 waypoints, 64 slots, B = 8192, pools 2^18 / 2^14) with
+    obstacles 8..31 moved 3 m away along y: every obstacle is still
+    interpolated and tested, but the problem is solvable before the forward
+    pool fills (about 64 iterations of 4096 forward workers)."""
+    prob = scenes.arm7rr(seed)
+    prob.wp[8:, :, 1] += 3.0
+    return prob
+
+
 def _no_recycling(prob):
     prob.params.no_recycling = 1
     return prob
@@ -231,6 +242,9 @@ PLAN_CASES = [
     ("arm7-rr-8", lambda: _small(scenes.arm7rr(8, n_obs=8, attempt=3), 1024, 1 << 16, 1 << 13, 16), 400, True),
     ("arm6-static-ir-14", lambda: _small(scenes.arm6static(14, attempt=42), 1024, 1 << 16, 1 << 13, 8), 600, True),
     ("arm6-static-ir-24", lambda: _small(scenes.arm6static(24, attempt=9), 1024, 1 << 16, 1 << 13, 8), 600, True),
+    # the recycling workload's full shape (start and goal accepted at attempt 0)
+    ("arm7-rr-c3-22", lambda: _c3_parked(22), 40, True),
+    ("arm7-rr-c3-26", lambda: _c3_parked(26), 40, True),
 ]
 
 
