@@ -103,6 +103,11 @@ def pick_problem(workload, lib, first_seed=0, limit=64, **kw):
     raise RuntimeError("no usable problem found")
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result stays alone on stdout)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -181,9 +186,11 @@ def _with(prob, B, cap_fwd, cap_bwd, planner_seed):
     return p
 
 
-def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_paths=False):
+def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_paths=False, iters_per_launch=4):
     """Plan all problems as one batch; returns the batch result and the summed
-    work counters of its members (keep_paths: the solved members' paths)."""
+    work counters of its members (keep_paths: the solved members' paths).
+    A member's first-solution time is resolved to the launch (graph of
+    iters_per_launch iterations) that found it."""
     from paper_2609_30533_amd import autotune
     if table is not None:
         for p in probs:
@@ -194,13 +201,15 @@ def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_
             autotune.apply(p, table, g)
     if proposal is not None:
         proposal.install(gps, probs, mix)
-    b = lib.Batch(gps)
+    b = lib.Batch(gps, iters_per_launch=iters_per_launch)
     w0 = [g.work_counters() for g in gps]
     r = b.plan(max_ms=budget_ms)
     w1 = [g.work_counters() for g in gps]
     edges = sum((a["edges"] - z["edges"]) + (a["bridges"] - z["bridges"]) for a, z in zip(w1, w0))
-    states = sum((a["edge_states"] - z["edge_states"]) + (a["bridge_states"] - z["bridge_states"])
-                 for a, z in zip(w1, w0))
+    per = [(a["edge_states"] - z["edge_states"]) + (a["bridge_states"] - z["bridge_states"]) for a, z in zip(w1, w0)]
+    states = sum(per)
+    # algorithmic flops of the decided states, each member at its own cost per state
+    flops = sum(n * flops_per_state(p) for n, p in zip(per, probs))
     if keep_paths:
         r["paths"] = {i: g.path() for i, g in enumerate(gps) if r["first_iter"][i] >= 0}
     b.close()
@@ -208,6 +217,7 @@ def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_
         g.close()
     r["edges"] = edges
     r["states"] = states
+    r["flops"] = flops
     return r
 
 
@@ -260,9 +270,11 @@ def ttfs_section(lib, args, validate):
     U = {c: {} for c in t}                                     # arrival at the end of the run
     it1 = {c: {} for c in t}                                   # iterations to the first solution
     for ps in args.planner_seeds:
-        batch_probs = [_with(p, 256, 1 << 16, 1 << 13, ps) for _, p in base]
+        batch_probs = [_with(p, args.ttfs_batch_samples, 1 << 16, 1 << 13, ps) for _, p in base]
         for c, prop in conds:
-            r = batched_run(lib, batch_probs, args.ttfs_ms, proposal=prop, keep_paths=True)
+            progress("time to first solution: planner seed %d, %s batch of %d problems" % (ps, c, n))
+            # one iteration per launch: first solutions timed to the iteration
+            r = batched_run(lib, batch_probs, args.ttfs_ms, proposal=prop, keep_paths=True, iters_per_launch=1)
             for i, path in r["paths"].items():
                 key = (base[i][0], ps)
                 t[c][key] = float(r["first_ms"][i])
@@ -271,6 +283,7 @@ def ttfs_section(lib, args, validate):
                 if path["rc"] == 0:
                     validate.append((batch_probs[i], path["states"], path["U"], path["C"]))
         solved_any = sorted({k[0] for c, _ in conds for k in t[c] if k[1] == ps})
+        progress("time to first solution: planner seed %d, plain one at a time on %d problems" % (ps, len(solved_any)))
         for s in solved_any:
             p = _with(dict(base)[s], 4096, 1 << 18, 1 << 16, ps)
             g = lib.Problem(p)
@@ -291,9 +304,10 @@ def ttfs_section(lib, args, validate):
     out = {
         "ttfs_workload": "arm6 evaluation seeds 0..%d with start and goal accepted by the library (%d problems), "
                          "planner seeds %s; plain = one problem at a time, B=4096, %.0f ms budget, stop at the "
-                         "first solution; batched = all problems in one batch, B=256 each, %.0f ms; learned and "
-                         "untrained networks mixed 50/50" % (args.ttfs_problems - 1, n, list(args.planner_seeds),
-                                                              args.ttfs_single_ms, args.ttfs_ms),
+                         "first solution; batched = all problems in one batch, B=%d each, %.0f ms, first solutions timed "
+                         "to the iteration; learned and untrained networks mixed 50/50" % (
+                             args.ttfs_problems - 1, n, list(args.planner_seeds), args.ttfs_single_ms,
+                             args.ttfs_batch_samples, args.ttfs_ms),
         "ttfs_problems": n,
         "ttfs_runs": n * len(args.planner_seeds),
     }
@@ -346,8 +360,8 @@ def ttfs_section(lib, args, validate):
                 queue[i] = ts + r["first_ms"]
             g.close()
         plain_queue_wall = (time.perf_counter() - t0) * 1e3
-        lq = batched_run(lib, [_with(base[i][1], 256, 1 << 16, 1 << 13, 1) for i in range(Q)], args.queue_ms,
-                         proposal=trained)
+        lq = batched_run(lib, [_with(base[i][1], args.ttfs_batch_samples, 1 << 16, 1 << 13, 1) for i in range(Q)],
+                         args.queue_ms, proposal=trained, iters_per_launch=1)
         qcommon = [i for i in queue if math.isfinite(lq["first_ms"][i])]
         out.update({
             "queue_workload": "the first %d evaluation problems submitted at once; %.0f ms budget per problem "
@@ -381,6 +395,9 @@ def batched_section(lib, args):
         "batched_solved": int(r["n_solved"]),
         "batched_ttfs_ms_median": float(np.median(fm)) if len(fm) else None,
         "batched_states": int(r["states"]),
+        # the members' states differ in cost (2-DOF discs to 7-DOF arms against
+        # 64 obstacles): the algorithmic rate over the whole batched run
+        "batched_edge_check_tflops": r["flops"] / (r["total_ms"] * 1e-3) / 1e12,
         "tuning_table": "paper_2609_30533_amd/data/tuning.json" if table else None,
     }
 
@@ -685,6 +702,8 @@ def main():
     ap.add_argument("--queue-ms", type=float, default=100.0)
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
+    ap.add_argument("--ttfs-batch-samples", type=int, default=32,
+                    help="samples per iteration of each problem in the time-to-first-solution batches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-reference", type=int, default=0,
                     help="only copy this many MiB device to device three times (the reference kernel that "
@@ -743,14 +762,20 @@ def main():
     # the headline problem: the first seed of the arm workload whose own draw
     # of start and goal is accepted (seed 1)
     seed, prob, gp = pick_problem("arm6", lib, first_seed=1)
+    progress("headline: %d warm-up and %d timed iterations" % (args.warmup, args.steps))
     m = single_run(gp, prob, args)
+    progress("headline: %.4f ms per iteration" % (m["elapsed"] * 1e3 / args.steps))
     configs = [] if args.no_configs else config_rows(lib, args)
     to_validate = []
     ttfs = ttfs_section(lib, args, to_validate) if args.ttfs_problems > 0 else {}
+    if args.batch_problems > 0:
+        progress("heterogeneous batch of %d problems" % args.batch_problems)
     batched = batched_section(lib, args) if args.batch_problems > 0 else {}
     cpu = None
     if not args.no_cpu_baseline:
+        progress("oracle baseline on the host cores")
         cpu = cpu_baseline(prob, args.cpu_seconds)
+        progress("oracle re-validation of %d paths" % len(to_validate))
         # every compared path re-checked by the oracle
         import oracle
         bad = [i for i, (p, st, U, C) in enumerate(to_validate)

@@ -225,6 +225,9 @@ static int batch_build(st_batch *b) {
         set_error("batch graph instantiation failed: %s", hipGetErrorString(e2));
         return ST_EHIP;
     }
+    // the graph's device-side set-up now, not in the first launch of a plan
+    ST_HIP(hipGraphUpload(b->graph, b->cap));
+    ST_HIP(hipStreamSynchronize(b->cap));
     return ST_OK;
 }
 

@@ -356,21 +356,22 @@ __global__ __launch_bounds__(256) void k_edge_finish(EdgeArgs a) { edge_finish_b
 // Many problems per launch: blockIdx.y selects the problem's record (through
 // `members` for the per-scene-class item kernel); blocks past the problem's
 // own grid leave at once.
-__global__ __launch_bounds__(256) void k_edge_plan_multi(const EdgeArgs *av) {
+__global__ __launch_bounds__(256) void k_edge_plan_multi(const EdgeArgs *__restrict__ av) {
     const EdgeArgs &a = av[blockIdx.y];
     if ((int)blockIdx.x >= a.nb_edge) return;
     edge_plan_body(a, blockIdx.x);
 }
 
 template <int KIND, int OT, int OBS, int SPLIT>
-__global__ __launch_bounds__(256) void k_edge_items_multi(const EdgeArgs *av, const int32_t *members) {
+__global__ __launch_bounds__(256) void k_edge_items_multi(const EdgeArgs *__restrict__ av,
+                                                          const int32_t *__restrict__ members) {
     extern __shared__ float4 lds[];
     const EdgeArgs &a = av[members[blockIdx.y]];
     if ((int)blockIdx.x >= a.nb_items) return;
     edge_items_body<KIND, OT, OBS, SPLIT>(a, lds, blockIdx.x, a.nb_items);
 }
 
-__global__ __launch_bounds__(256) void k_edge_finish_multi(const EdgeArgs *av) {
+__global__ __launch_bounds__(256) void k_edge_finish_multi(const EdgeArgs *__restrict__ av) {
     const EdgeArgs &a = av[blockIdx.y];
     if ((int)blockIdx.x >= a.nb_edge) return;
     edge_finish_body(a, blockIdx.x);

@@ -106,7 +106,8 @@ template <int KIND>
 constexpr int sample_lanes() { return KIND == kTranslate ? 1 : 4; }
 
 template <int KIND, int OT, int OBS, bool MULTI>
-__global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs *av, const int32_t *members) {
+__global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs *__restrict__ av,
+                                                const int32_t *__restrict__ members) {
     extern __shared__ float4 lds[];
     const SampleArgs &a = MULTI ? av[members[blockIdx.y]] : a0;
     if (MULTI && (int)blockIdx.x >= a.nb) return;
@@ -290,7 +291,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
 // set's bucket, its empty key, and the snapshot of the batch.  One block; the
 // counters are overwritten.
 template <bool MULTI>
-__global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *av) {
+__global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *__restrict__ av) {
     const PrepArgs &a = MULTI ? av[blockIdx.y] : a0;
     __shared__ int cnt[kMaxPools];
     const int tid = threadIdx.x;
@@ -356,7 +357,8 @@ constexpr int kMinSliceNodes = 64;  // nearest-node scans: nodes per slice at le
 // 256 (each thread loads one node, coalesced per SoA row), and the next
 // round is fetched into registers while the current one is scanned.
 template <int MODE, bool MULTI>
-__global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *av, const int32_t *members) {
+__global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__restrict__ av,
+                                                 const int32_t *__restrict__ members) {
     __shared__ __align__(16) float sx[kTileQ][8];
     __shared__ float sT[kTileQ];
     __shared__ int32_t sI[kTileQ];
@@ -667,7 +669,7 @@ __device__ __forceinline__ bool steer_worker(const SteerArgs &a, int64_t w, floa
 }
 
 template <bool MULTI>
-__global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *av) {
+__global__ __launch_bounds__(256) void k_steer(SteerArgs a0, const SteerArgs *__restrict__ av) {
     const SteerArgs &a = MULTI ? av[blockIdx.y] : a0;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= a.B) return;
@@ -702,8 +704,9 @@ __global__ __launch_bounds__(64 * kFlatWaves) void k_steer_flat(SteerArgs sa, Ed
 }
 
 template <int KIND, int OT, int OBS>
-__global__ __launch_bounds__(64 * kFlatWaves) void k_steer_flat_multi(const SteerArgs *sv, const EdgeArgs *ev,
-                                                                     const int32_t *members) {
+__global__ __launch_bounds__(64 * kFlatWaves) void k_steer_flat_multi(const SteerArgs *__restrict__ sv,
+                                                                     const EdgeArgs *__restrict__ ev,
+                                                                     const int32_t *__restrict__ members) {
     extern __shared__ float4 lds[];
     const int m = members[blockIdx.y];
     const EdgeArgs &ea = ev[m];
@@ -717,7 +720,7 @@ __global__ __launch_bounds__(64 * kFlatWaves) void k_steer_flat_multi(const Stee
 
 
 template <bool MULTI>
-__global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs *av) {
+__global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs *__restrict__ av) {
     __shared__ int wsum[32];
     __shared__ int s_total, s_last;
     __shared__ int s_bcnt[2], s_bbase[2];  // bridge bucket places of this pass
@@ -898,8 +901,9 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
 // advance.  The per-edge records (state count, least hit) are the plan
 // step's; the finish step runs in the publish kernel.
 template <int KIND, int OT, int OBS, bool MULTI>
-__global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a0, EdgeArgs ea0, const BridgeArgs *av,
-                                                      const EdgeArgs *ev, const int32_t *members) {
+__global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a0, EdgeArgs ea0, const BridgeArgs *__restrict__ av,
+                                                      const EdgeArgs *__restrict__ ev,
+                                                      const int32_t *__restrict__ members) {
     extern __shared__ float4 lds[];
     const int mi = MULTI ? members[blockIdx.y] : 0;
     const BridgeArgs &a = MULTI ? av[mi] : a0;
@@ -1146,8 +1150,8 @@ __device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, f
 }
 
 template <bool MULTI>
-__global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishArgs *av, RootsArgs r0,
-                                                  const RootsArgs *rv) {
+__global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishArgs *__restrict__ av, RootsArgs r0,
+                                                  const RootsArgs *__restrict__ rv) {
     __shared__ float sU[1024], sC[1024];
     __shared__ int sW[1024];
     const PublishArgs &a = MULTI ? av[blockIdx.y] : a0;
@@ -1418,8 +1422,8 @@ static hipError_t dalloc(T **p, size_t n) {
 
 void work_free(st_problem *p) {
     Work &w = p->work;
-    void *bufs[] = {w.dir, w.flags, w.grp, w.T, w.qr, w.tr, w.nn_key, w.tiles, w.n_tiles, w.bcnt, w.border_nn, w.border_br,
-                    w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit, w.status, w.parent, w.new_idx, w.cost_new,
+    void *bufs[] = {w.dir, w.flags, w.grp, w.T, w.qr, w.tr, w.nn_key, w.tiles, w.n_tiles, w.bcnt, w.border_nn,
+                    w.border_br, w.xn, w.xnew, w.edge_valid, w.edge_free, w.first_hit, w.status, w.parent, w.new_idx, w.cost_new,
                     w.rootT_new, w.br_key, w.br_idx, w.bridge, w.xb, w.br_valid, w.br_free, w.Up, w.Cp};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
@@ -1866,6 +1870,9 @@ static int capture_iterations(st_problem *p, int n, hipGraphExec_t *out) {
         set_error("graph instantiation failed: %s", hipGetErrorString(e2));
         return ST_EHIP;
     }
+    // the graph's device-side set-up now, not in its first replay
+    ST_HIP(hipGraphUpload(*out, cs));
+    ST_HIP(hipStreamSynchronize(cs));
     return ST_OK;
 }
 
