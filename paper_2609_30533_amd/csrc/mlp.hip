@@ -209,19 +209,36 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         }
 }
 
-// out[i] = sum over z of part[z n + i], in split order (deterministic)
-__global__ void k_sum_splits(int64_t n, int S, const float *part, float *out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// out[i] = sum over z of part[z n + i]: a block takes 16 outputs, thread
+// (o, g) sums the splits z = g (mod 16) of output o in order, and the 16
+// group sums are added in group order (deterministic for given n and S)
+__global__ __launch_bounds__(256) void k_sum_splits(int64_t n, int S, const float *part, float *out) {
+    __shared__ float red[16][17];
+    const int o = threadIdx.x & 15, g = threadIdx.x >> 4;
+    const int64_t i = (int64_t)blockIdx.x * 16 + o;
     float s = 0.f;
-    for (int z = 0; z < S; ++z) s += part[(int64_t)z * n + i];
-    out[i] = s;
+    if (i < n)
+        for (int z = g; z < S; z += 16) s += part[(int64_t)z * n + i];
+    red[g][o] = s;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        float t = 0.f;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) t += red[k][o];
+        out[i] = t;
+    }
+}
+
+static hipError_t sum_splits(hipStream_t s, int64_t n, int S, const float *part, float *out) {
+    k_sum_splits<<<(int)((n + 15) / 16), 256, 0, s>>>(n, S, part, out);
+    return hipGetLastError();
 }
 
 // Split-K factor of a product with a long reduction (weight gradients: the
 // reduction runs over the examples): enough blocks to fill the device, at
 // least 256 k per split, at most kMaxSplits splits.
 constexpr int kMaxSplits = 256;
+constexpr int kMaxColSplits = 1024;  // row chunks of a bias column sum at most
 static int gemm_splits(int M, int N, int64_t K, int *kc) {
     const int64_t tiles = (int64_t)((M + 63) / 64) * ((N + 63) / 64);
     int64_t S = std::min<int64_t>((2048 + tiles - 1) / tiles, K / 256);
@@ -263,9 +280,7 @@ static hipError_t gemm(hipStream_t s, bool ak, const float *A, int64_t lda, bool
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || S == 1) return e;
     if (ldc != N) return hipErrorInvalidValue;  // split results are stored dense
-    const int64_t n = (int64_t)M * N;
-    k_sum_splits<<<(int)((n + 255) / 256), 256, 0, s>>>(n, S, ws, C);
-    return hipGetLastError();
+    return sum_splits(s, (int64_t)M * N, S, ws, C);
 }
 
 // encoder: phi = gelu(pre_e); masked max over obstacles (first maximum wins);
@@ -323,13 +338,13 @@ __global__ __launch_bounds__(256) void k_colsum_part(int M, int N, int rc, const
 }
 
 static hipError_t colsum(hipStream_t s, int64_t M, int N, const float *X, float *out, float *ws) {
-    const int S = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxSplits, M / 256));
+    // row chunks of at least 64 rows (16 per thread), at most kMaxColSplits
+    const int S = (int)std::max<int64_t>(1, std::min<int64_t>(kMaxColSplits, M / 64));
     const int rc = (int)((M + S - 1) / S);
     k_colsum_part<<<dim3((N + 63) / 64, S), 256, 0, s>>>((int)M, N, rc, X, ws);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_sum_splits<<<(N + 255) / 256, 256, 0, s>>>(N, S, ws, out);
-    return hipGetLastError();
+    return sum_splits(s, N, S, ws, out);
 }
 
 // Reductions over the kComp lanes of one example (groups of 8 lanes).
@@ -515,7 +530,7 @@ int st_mlp_create(int32_t max_batch, int32_t max_obstacles, st_mlp **out) {
         // the largest split-K workspace any weight-gradient product or bias
         // column sum of a batch up to max_batch rows needs
         const int shapes[4][3] = {{kWidth, kOut, 0}, {kWidth, kWidth, 0}, {kDin, kWidth, 0}, {kEncIn, kEncOut, 1}};
-        int64_t need = (int64_t)kMaxSplits * kWidth;
+        int64_t need = (int64_t)kMaxColSplits * kWidth;
         for (const auto &sh : shapes) {
             int kc = 0;
             const int64_t K = sh[2] ? MO : M;
