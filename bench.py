@@ -623,7 +623,7 @@ def report(args, seed, prob, gp, m, ttfs, batched, cpu, configs):
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE and WRITE_SIZE, copy-scaled)",
                      "traffic_source": traffic_src,
                      "kernel": "edge check: extension launch k_steer_flat (steering fused with the check), "
-                               "bridge launch k_edge_plan + k_edge_items",
+                               "bridge launch k_bridge_check (merge fused with the first 64 states) + k_edge_items",
                      "flops_per_state": W, "states": states, "launches": launches,
                      "avg_launch_ms": ms_edge / max(launches, 1),
                      "timing": "HIP events on the launch stream around each edge-check launch, %d iterations "
