@@ -1152,8 +1152,8 @@ __device__ __forceinline__ bool lex_less(float u1, float c1, int w1, float u2, f
 template <bool MULTI>
 __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishArgs *__restrict__ av, RootsArgs r0,
                                                   const RootsArgs *__restrict__ rv) {
-    __shared__ float sU[1024], sC[1024];
-    __shared__ int sW[1024];
+    __shared__ float sU[16], sC[16];  // one candidate per wave (1024 threads)
+    __shared__ int sW[16];
     const PublishArgs &a = MULTI ? av[blockIdx.y] : a0;
     const int tid = threadIdx.x;
     const Work &k = a.w;
@@ -1186,18 +1186,38 @@ __global__ __launch_bounds__(1024) void k_publish(PublishArgs a0, const PublishA
         states += __shfl_down(states, o, 64);
         edges += __shfl_down(edges, o, 64);
     }
-    sU[tid] = bu;
-    sC[tid] = bc;
-    sW[tid] = bw;
-    __syncthreads();
-    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-        if (tid < s && lex_less(sU[tid + s], sC[tid + s], sW[tid + s], sU[tid], sC[tid], sW[tid])) {
-            sU[tid] = sU[tid + s];
-            sC[tid] = sC[tid + s];
-            sW[tid] = sW[tid + s];
+    // the lexicographic minimum: within each wave by shuffles, then over the
+    // waves' results by wave 0 (every lane of a wave ends with its minimum)
+    auto wave_min = [&](float &u, float &c, int &wk) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const float ou = __shfl_xor(u, o, 64), oc = __shfl_xor(c, o, 64);
+            const int ow = __shfl_xor(wk, o, 64);
+            if (lex_less(ou, oc, ow, u, c, wk)) {
+                u = ou;
+                c = oc;
+                wk = ow;
+            }
         }
-        __syncthreads();
+    };
+    wave_min(bu, bc, bw);
+    const int nwv = (int)(blockDim.x >> 6);
+    if ((tid & 63) == 0) {
+        sU[tid >> 6] = bu;
+        sC[tid >> 6] = bc;
+        sW[tid >> 6] = bw;
     }
+    __syncthreads();
+    if (tid < 64) {
+        float u = tid < nwv ? sU[tid] : INFINITY, c = tid < nwv ? sC[tid] : INFINITY;
+        int wk = tid < nwv ? sW[tid] : -1;
+        wave_min(u, c, wk);
+        if (tid == 0) {
+            sU[0] = u;
+            sC[0] = c;
+            sW[0] = wk;
+        }
+    }
+    __syncthreads();
     if (tid == 0) {
         PlanDev *pl = a.pl;
         const int w = sW[0];

@@ -484,3 +484,35 @@ def test_capacity_exhausted_is_reported(oracle_lib):
     assert res["rc"] == lib.ST_ECAPACITY and res["states"] is None
     c = gp.export()["counts"]
     assert c[0] <= 24 and np.all(c[1:] <= 6)
+
+
+@pytest.mark.parametrize("name,make", [
+    ("arm6-ir", lambda: _small(scenes.arm6(2), 1024, 1 << 15, 1 << 12, 8)),
+    ("arm7-rr", lambda: _small(scenes.arm7rr(2, n_obs=16), 1024, 1 << 15, 1 << 12, 16)),
+    ("disc2d-ir", lambda: _small(scenes.disc2d(3), 512)),
+], ids=["arm6-ir", "arm7-rr", "disc2d-ir"])
+def test_iterate_equals_sample_and_extend(name, make):
+    """The planner's own iterations (the sampler buckets its workers by node
+    set, the extend step runs without the separate bucketing kernel, graph
+    replays) and the same iterations through st_sample_batch +
+    st_extend_batch (caller-given samples, bucketed by k_prep) build the same
+    trees, node for node, and the same incumbent."""
+    from paper_2609_30533_amd.lib import Problem
+    torch = torch_cuda()
+    banner("iterate vs sample+extend %s" % name)
+    ga, gb = Problem(make()), Problem(make())
+    n = 12
+    ga.iterate(n)
+    for it in range(n):
+        gb.extend(gb.sample(it))
+    torch.cuda.synchronize()
+    ea, eb = ga.export(), gb.export()
+    assert np.array_equal(ea["counts"], eb["counts"]), (ea["counts"], eb["counts"])
+    assert ea["counts"].sum() > 0
+    prm = ga.prob.params
+    for p, c in enumerate(ea["counts"]):
+        base = 0 if p == 0 else prm.cap_fwd + (p - 1) * prm.cap_bwd
+        for k in ("x", "parent", "cost", "rootT"):
+            assert np.array_equal(ea[k][base:base + c], eb[k][base:base + c]), (k, p)
+    ia, ib = ga.info(), gb.info()
+    assert ia["U"] == ib["U"] and ia["C"] == ib["C"] and ia["iter"] == ib["iter"] == n
