@@ -186,7 +186,8 @@ def _with(prob, B, cap_fwd, cap_bwd, planner_seed):
     return p
 
 
-def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_paths=False, iters_per_launch=4):
+def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_paths=False, iters_per_launch=4,
+                lanes_bridge=0):
     """Plan all problems as one batch; returns the batch result and the summed
     work counters of its members (keep_paths: the solved members' paths).
     A member's first-solution time is resolved to the launch (graph of
@@ -196,6 +197,9 @@ def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_
         for p in probs:
             autotune.apply(p, table)
     gps = [lib.Problem(p, problem_id=i) for i, p in enumerate(probs)]
+    if lanes_bridge:
+        for g in gps:
+            g.set_tuning(lanes_bridge=lanes_bridge)
     if table is not None:
         for p, g in zip(probs, gps):
             autotune.apply(p, table, g)
@@ -274,7 +278,8 @@ def ttfs_section(lib, args, validate):
         for c, prop in conds:
             progress("time to first solution: planner seed %d, %s batch of %d problems" % (ps, c, n))
             # one iteration per launch: first solutions timed to the iteration
-            r = batched_run(lib, batch_probs, args.ttfs_ms, proposal=prop, keep_paths=True, iters_per_launch=1)
+            r = batched_run(lib, batch_probs, args.ttfs_ms, proposal=prop, keep_paths=True, iters_per_launch=1,
+                            lanes_bridge=args.ttfs_lanes_bridge)
             for i, path in r["paths"].items():
                 key = (base[i][0], ps)
                 t[c][key] = float(r["first_ms"][i])
@@ -287,6 +292,8 @@ def ttfs_section(lib, args, validate):
         for s in solved_any:
             p = _with(dict(base)[s], 4096, 1 << 18, 1 << 16, ps)
             g = lib.Problem(p)
+            if args.ttfs_lanes_bridge:
+                g.set_tuning(lanes_bridge=args.ttfs_lanes_bridge)
             r = g.plan(max_ms=args.ttfs_single_ms, stop_at_first=True, iters_per_sync=1)
             if r["first_iter"] >= 0 and r["rc"] == 0:
                 t["plain"][(s, ps)] = r["first_ms"]
@@ -305,9 +312,10 @@ def ttfs_section(lib, args, validate):
         "ttfs_workload": "arm6 evaluation seeds 0..%d with start and goal accepted by the library (%d problems), "
                          "planner seeds %s; plain = one problem at a time, B=4096, %.0f ms budget, stop at the "
                          "first solution; batched = all problems in one batch, B=%d each, %.0f ms, first solutions timed "
-                         "to the iteration; learned and untrained networks mixed 50/50" % (
+                         "to the iteration; learned and untrained networks mixed 50/50; %s lanes per bridge "
+                         "chunk in both" % (
                              args.ttfs_problems - 1, n, list(args.planner_seeds), args.ttfs_single_ms,
-                             args.ttfs_batch_samples, args.ttfs_ms),
+                             args.ttfs_batch_samples, args.ttfs_ms, args.ttfs_lanes_bridge or "default"),
         "ttfs_problems": n,
         "ttfs_runs": n * len(args.planner_seeds),
     }
@@ -702,6 +710,9 @@ def main():
     ap.add_argument("--queue-ms", type=float, default=100.0)
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
+    ap.add_argument("--ttfs-lanes-bridge", type=int, default=32,
+                    help="lanes per bridge chunk of every time-to-first-solution problem, plain and batched "
+                         "(0: the library's default)")
     ap.add_argument("--ttfs-batch-samples", type=int, default=32,
                     help="samples per iteration of each problem in the time-to-first-solution batches")
     ap.add_argument("--no-cpu-baseline", action="store_true")
