@@ -54,14 +54,14 @@ __device__ __forceinline__ int worker_pool(int8_t dir, int32_t grp) { return dir
 // The windows' lo, hi and cum arrays are read from wlo, whi, wcum (LDS when
 // the sampler staged them, else the device copies in w).
 __device__ double ir_root_time(const WindowsDev &w, const double *wlo, const double *whi, const double *wcum,
-                               const PlanDev *pl, int g, const uint32_t *u, float p_guided) {
-    const double L = w.L, Ubar = pl->Ubar, G = pl->G;
+                               double Ubar, double G, int jstar, int g, const uint32_t *u, float p_guided) {
+    const double L = w.L;
     const int N = w.N;
-    if (unit24f(u[1]) < p_guided && G > 0.0 && pl->jstar > 0) {
+    if (unit24f(u[1]) < p_guided && G > 0.0 && jstar > 0) {
         const double c_lo = G * g / N, c_hi = G * (g + 1) / N;
         const double c = c_lo + unit24d(u[2]) * (c_hi - c_lo);
         // window j with cum[j] <= c < cum[j] + len_j
-        int lo = 0, hi = pl->jstar - 1;
+        int lo = 0, hi = jstar - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (wcum[mid] <= c) lo = mid;
@@ -113,6 +113,16 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
     if (MULTI && (int)blockIdx.x >= a.nb) return;
     const SceneDev &sc = a.sc;
     const bool ir = a.variant == ST_INTERVAL_ROOT;
+    // the plan state the sampler reads, loaded ahead of the staging barrier
+    // so that its latency overlaps the staging (a negative iteration means
+    // "the planner's own counter", as in graph replays)
+    const PlanDev *pl = a.pl;
+    const int64_t iter = a.iter >= 0 ? a.iter : (int64_t)pl->iter;
+    const float prop_mix = pl->prop_mix, U_now = pl->U;
+    const int32_t done = pl->done, n_active = pl->n_active, jstar = pl->jstar;
+    const double Ubar = pl->Ubar, Gsum = pl->G;
+    const bool snap_block = a.bcnt && blockIdx.x == 0;
+    const int32_t snap_count = snap_block && (int)threadIdx.x < a.n_pools ? pl->count[threadIdx.x] : 0;
     // interval root: the guided windows go to LDS behind the scene, so the
     // binary search of a root time reads LDS, not device memory
     const int nwl = ir ? a.nw_lds : 0;
@@ -129,11 +139,8 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
     const int64_t w = gt / SL;
     const int part = (int)(gt % SL);
     const bool act = w < a.B;
-    const PlanDev *pl = a.pl;
-    // a negative iteration means "the planner's own counter" (graph replays)
-    const int64_t iter = a.iter >= 0 ? a.iter : (int64_t)pl->iter;
     uint32_t u[28];
-    const bool learned = pl->prop_mix > 0.f;
+    const bool learned = prop_mix > 0.f;
     const int nblk = learned ? 7 : 4;
 #pragma unroll
     for (int b = 0; b < 7; ++b) {
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
         q[j] = j < sc.d ? sc.q_lo[j] + unit24f(u[4 + j]) * (sc.q_hi[j] - sc.q_lo[j]) : 0.f;
     bool check_root = false;
     // learned draw: (q, t) from the mixture, T from the arrival histogram
-    const bool use_net = learned && unit24f(u[13]) < pl->prop_mix;
+    const bool use_net = learned && unit24f(u[13]) < prop_mix;
     float y7 = 0.f;
     if (use_net) {
         flags |= ST_FLAG_LEARNED;
@@ -181,14 +188,14 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
     }
     if (ir) {
         g = index24(u[0], a.N);
-        if (!act || pl->done) {
+        if (!act || done) {
             flags |= ST_FLAG_SKIP;
         } else if (use_net) {
             int b = 0;
             while (b < 31 && !(unit24f(u[15]) < pl->prop_hcum[b])) ++b;
             const double w = (a.t_max - a.t_min) / 32.0;
             const double Td = a.t_min + ((double)b + unit24d(u[24])) * w;
-            const double L = a.win.L, Ubar = pl->Ubar;
+            const double L = a.win.L;
             if (!(Td >= L && Td < Ubar)) {
                 flags |= ST_FLAG_SKIP;
             } else {
@@ -199,13 +206,14 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
                 check_root = !(flags & ST_FLAG_SKIP);
             }
         } else {
-            T = nwl > 0 ? (float)ir_root_time(a.win, wl, wl + nwl, wl + 2 * nwl, pl, g, u, a.p_guided)
-                        : (float)ir_root_time(a.win, a.win.lo, a.win.hi, a.win.cum, pl, g, u, a.p_guided);
+            T = nwl > 0 ? (float)ir_root_time(a.win, wl, wl + nwl, wl + 2 * nwl, Ubar, Gsum, jstar, g, u, a.p_guided)
+                        : (float)ir_root_time(a.win, a.win.lo, a.win.hi, a.win.cum, Ubar, Gsum, jstar, g, u,
+                                              a.p_guided);
             check_root = true;
         }
     } else if (act && dir == 1) {
         const int64_t k = w >> 1;
-        const int na = pl->n_active;
+        const int na = n_active;
         if (na == 0) {
             flags |= ST_FLAG_SKIP;
         } else {
@@ -214,6 +222,8 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
         }
     }
     if (ir) {
+        // the group's earliest root, loaded ahead of the root check's arithmetic
+        const float min_root = check_root && dir == 1 ? pl->minRootT[g] : 0.f;
         // the proposed root (q_g, T) is checked at its own time
         const bool hit = goal_hits<OT, OBS, SL>(sc, lds, T, check_root, part);
         if (check_root) {
@@ -237,7 +247,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
             } else {
                 tr = lo + unit24f(u[11]) * (hi - lo);
             }
-            if (dir == 1 && (!(pl->minRootT[g] < pl->U) || unit24f(u[12]) <= a.p_new)) flags |= ST_FLAG_USE_NEW;
+            if (dir == 1 && (!(min_root < U_now) || unit24f(u[12]) <= a.p_new)) flags |= ST_FLAG_USE_NEW;
         }
     }
     if (a.bcnt) {
@@ -262,12 +272,12 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
         __syncthreads();
         if (set >= 0) a.border[(int64_t)set * a.B + s_bbase[set] + pos] = (int32_t)w;
         if (act && part == 0) a.keys[w] = kNoKey;
-        if (blockIdx.x == 0) {
+        if (snap_block) {
             PlanDev *plw = const_cast<PlanDev *>(pl);
             const int tid = threadIdx.x;
-            if (tid < a.n_pools) plw->count_snap[tid] = pl->count[tid];
+            if (tid < a.n_pools) plw->count_snap[tid] = snap_count;
             if (tid == 0) {
-                plw->U_snap = pl->U;
+                plw->U_snap = U_now;
                 plw->improved = 0;
             }
         }
@@ -368,6 +378,8 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__
     if (MULTI && (int)blockIdx.y >= a.nch) return;
     const int t = blockIdx.x;
     const int tid = threadIdx.x;
+    const PlanDev *pl = a.pl;
+    const float U = a.use_snap ? pl->U_snap : pl->U;  // loaded ahead of the set-up barriers
     int4 tile;             // set, first query, queries, sigma
     int64_t qrow = -1;     // bucket row of the tile's queries (-1: identity order)
     if (a.bmode == 0) {
@@ -407,8 +419,6 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__
     const int set = tile.x, n = tile.z;
     const float sv = (float)tile.w * a.v;  // sigma * v
     const int d = a.tree.d;
-    const PlanDev *pl = a.pl;
-    const float U = a.use_snap ? pl->U_snap : pl->U;
     // pools of the set and their prefix sums: the counts are loaded by one
     // thread per pool, the prefix is formed from LDS
     const int p_lo = set >= 0 ? set : 1, p_hi = set >= 0 ? set + 1 : a.tree.n_pools;
