@@ -139,6 +139,8 @@ def _declare(L):
     L.orc_planner_bridge.argtypes = [C.c_void_p, C.c_int, f64, C.c_double, C.POINTER(C.c_double),
                                      C.POINTER(C.c_uint8)]
     L.orc_planner_bridge.restype = C.c_int64
+    L.orc_planner_recycle.argtypes = [C.c_void_p, C.c_double]
+    L.orc_planner_recycle.restype = C.c_int
     L.orc_planner_set_proposal.argtypes = [C.c_void_p, _opt(f64), C.c_double]
     L.orc_validate_path.argtypes = [S, C.c_int64, f64, C.c_double, C.c_double, C.c_double, C.c_char_p, C.c_int]
     L.orc_validate_path.restype = C.c_int
@@ -393,6 +395,12 @@ class Planner:
         b = self.lib.orc_planner_bridge(self.h, int(sigma), np.ascontiguousarray(x, dtype=np.float64),
                                         float(x_rootT), C.byref(arr), C.byref(amb))
         return int(b), arr.value, bool(amb.value)
+
+    def recycle(self, U):
+        """A strict drop of U to the given value followed by the recycling
+        update (Alg. 3), outside the extend step."""
+        if self.lib.orc_planner_recycle(self.h, float(U)) != 0:
+            raise ValueError("recycle: not a recycling planner or U not below the incumbent")
 
     def set_proposal(self, z, mix):
         self.lib.orc_planner_set_proposal(self.h, None if z is None else np.ascontiguousarray(z, dtype=np.float64),

@@ -1008,6 +1008,18 @@ int64_t orc_planner_bridge(const orc_planner *p, int sigma, const double *x, dou
     return best_bridge(p, p->count, p->U, sigma, x, x_rootT, arr, amb);
 }
 
+/* A strict drop of the incumbent arrival to U outside the extend step, for
+ * the recycling variant (test access to the Alg. 3 allocation update):
+ * U is set and the roots are deactivated and recycled as after an improving
+ * iteration.  Returns 0, or -1 for an interval-root planner or U not below
+ * the current incumbent. */
+int orc_planner_recycle(orc_planner *p, double U) {
+    if (p->sc.variant != ORC_RR || !(U < p->U)) return -1;
+    p->U = U;
+    rr_update(p);
+    return 0;
+}
+
 int orc_planner_extend(orc_planner *p, int64_t B, const int8_t *dir, const uint8_t *flags, const int32_t *grp,
                        const double *T, const double *qr, const double *tr,
                        /* outputs (any may be NULL) */

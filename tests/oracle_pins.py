@@ -11,10 +11,13 @@ Eq. 8, Sec. IV-B bridge ranking, the capacity reading of the batch commit),
 not from the oracle's code, and share nothing with it.
 """
 import math
+import os
 
 import numpy as np
 
 from paper_2609_30533_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 FLAG_SKIP, FLAG_USE_NEW, FLAG_LEARNED = 1, 2, 4
 ST_ADVANCED, ST_DROPPED = 2, 3
@@ -412,7 +415,54 @@ def pin_learned_draw_moments(oracle):
     assert abs(frac - 0.3) < 5 * math.sqrt(0.3 * 0.7 / n), frac
 
 
+def _rr_worked():
+    rows = {}
+    for line in open(os.path.join(GOLDEN, "rr_worked_example.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            k, rest = line.split(None, 1)
+            rows[k] = rest
+    return rows
+
+
+def pin_recycling_worked_example(oracle):
+    """Root recycling on a hand-worked scene (tests/golden/rr_worked_example.txt,
+    Sec. V / Alg. 3, readings 12-13): the initial slot roots and the roots
+    after a drop of U equal the values derived by hand.  Catches: strata over
+    the wrong index range (k dt <= H, or [L, H) after the drop instead of
+    k dt < U), a stratum's first grid time taken whether free or not,
+    occupied strata not skipped, donors taken with T >= U or in the wrong
+    order, a donor consumed by a stratum without a free index, the
+    generation not advanced."""
+    rows = _rr_worked()
+    wp = np.array([[float(v) for v in seg.split()] for seg in rows["wp"].split("|")])
+    prob = scenes.Problem(
+        name="rr-worked", d=2, kind=scenes.KIND_TRANSLATE, dh=np.zeros((2, 4)),
+        sphere_link=np.zeros(1, dtype=np.int32), sphere=scenes.f32(np.array([[0.0, 0.0, 0.0, 0.05]])),
+        q_lo=scenes.f32(np.zeros(2)), q_hi=scenes.f32(np.ones(2)), q_start=scenes.f32([0.3, 0.5]),
+        q_goal=scenes.f32([0.8, 0.5]), t_min=scenes.f32(2.0), t_max=scenes.f32(10.0), v_max=scenes.f32(1.0),
+        n_wp=np.array([len(wp)], dtype=np.int32), wp=scenes.f32(wp[None]), obs_r=scenes.f32([0.08]),
+        params=scenes.Params(variant=scenes.VARIANT_RR, n_groups=4, batch=64, eta=0.1, h=0.01, dt=0.02,
+                             cap_fwd=1 << 10, cap_bwd=1 << 8, seed=1),
+        seed=0)
+    pl = oracle.Planner(prob)
+    ints = lambda key: np.array([int(v) for v in rows[key].split()])
+    flts = lambda key: np.array([float(v) for v in rows[key].split()])
+    T, act, gen, k = pl.slots()
+    assert np.array_equal(k, ints("init.k")), k
+    assert np.allclose(T, flts("init.T"), atol=1e-12), T
+    assert np.array_equal(act, ints("init.active")), act
+    pl.recycle(float(rows["U"]))
+    T, act, gen, k = pl.slots()
+    assert np.array_equal(k, ints("after.k")), k
+    assert np.allclose(T, flts("after.T"), atol=1e-12), T
+    assert np.array_equal(act, ints("after.active")), act
+    assert np.array_equal(gen, ints("after.gen")), gen
+
+
+
 PINS = {
+    "recycling_worked_example": pin_recycling_worked_example,
     "bridge_ranking": pin_bridge_ranking,
     "eq8_max_speed_step": pin_eq8_max_speed_step,
     "validator_rejections": pin_validator_rejections,

@@ -74,6 +74,18 @@ MUTANTS = [
     ("learned-bin-off-by-one", "learned_draw_moments",
      [("while (b < 31 && !(unit24(u[15]) < p->prop_hcum[b])) ++b;",
        "while (b < 31 && !(unit24(u[15]) < p->prop_hcum[b + 1])) ++b;", 1)]),
+    ("recycle-init-ignores-free", "recycling_worked_example",
+     [("            if (!p->gfree[k - p->k_lo]) continue;\n            xg[p->sc.d] = grid_time(p, k);\n            p->slotT[s] = xg[p->sc.d];\n            p->slotK[s] = k;\n            p->slot_active[s] = 1;\n            push_node(p, 1 + s, xg, -1, 0.0, xg[p->sc.d]);\n            break;\n        }\n    }\n    rr_refresh_active(p);\n}\n\n/* Root recycling",
+       "            xg[p->sc.d] = grid_time(p, k);\n            p->slotT[s] = xg[p->sc.d];\n            p->slotK[s] = k;\n            p->slot_active[s] = 1;\n            push_node(p, 1 + s, xg, -1, 0.0, xg[p->sc.d]);\n            break;\n        }\n    }\n    rr_refresh_active(p);\n}\n\n/* Root recycling", 1)]),
+    ("recycle-occupied-strata-not-skipped", "recycling_worked_example",
+     [("        if (occupied) continue;\n", "        (void)occupied;\n", 1)]),
+    ("recycle-strata-below-H", "recycling_worked_example",
+     [("while (k_end <= p->k_hi && grid_time(p, k_end) < U) ++k_end;",
+       "while (k_end <= p->k_hi && grid_time(p, k_end) < p->H) ++k_end;", 1)]),
+    ("recycle-generation-kept", "recycling_worked_example",
+     [("            p->slot_gen[s]++;\n", "", 1)]),
+    ("recycle-donors-in-reverse", "recycling_worked_example",
+     [("            int s = donors[di++];", "            int s = donors[nd - 1 - di++];", 1)]),
     ("learned-wrong-mix", "learned_draw_moments",
      [("const int use_net = learned && unit24(u[13]) < p->prop_mix;",
        "const int use_net = learned && unit24(u[13]) < 0.5;", 1)]),

@@ -9,3 +9,4 @@ from tests import oracle_pins
 @pytest.mark.parametrize("name", sorted(oracle_pins.PINS))
 def test_oracle_pin(oracle_lib, name):
     oracle_pins.PINS[name](oracle_lib)
+
