@@ -434,17 +434,7 @@ def pin_recycling_worked_example(oracle):
     occupied strata not skipped, donors taken with T >= U or in the wrong
     order, a donor consumed by a stratum without a free index, the
     generation not advanced."""
-    rows = _rr_worked()
-    wp = np.array([[float(v) for v in seg.split()] for seg in rows["wp"].split("|")])
-    prob = scenes.Problem(
-        name="rr-worked", d=2, kind=scenes.KIND_TRANSLATE, dh=np.zeros((2, 4)),
-        sphere_link=np.zeros(1, dtype=np.int32), sphere=scenes.f32(np.array([[0.0, 0.0, 0.0, 0.05]])),
-        q_lo=scenes.f32(np.zeros(2)), q_hi=scenes.f32(np.ones(2)), q_start=scenes.f32([0.3, 0.5]),
-        q_goal=scenes.f32([0.8, 0.5]), t_min=scenes.f32(2.0), t_max=scenes.f32(10.0), v_max=scenes.f32(1.0),
-        n_wp=np.array([len(wp)], dtype=np.int32), wp=scenes.f32(wp[None]), obs_r=scenes.f32([0.08]),
-        params=scenes.Params(variant=scenes.VARIANT_RR, n_groups=4, batch=64, eta=0.1, h=0.01, dt=0.02,
-                             cap_fwd=1 << 10, cap_bwd=1 << 8, seed=1),
-        seed=0)
+    prob, rows = rr_worked_problem()
     pl = oracle.Planner(prob)
     ints = lambda key: np.array([int(v) for v in rows[key].split()])
     flts = lambda key: np.array([float(v) for v in rows[key].split()])
@@ -458,6 +448,22 @@ def pin_recycling_worked_example(oracle):
     assert np.allclose(T, flts("after.T"), atol=1e-12), T
     assert np.array_equal(act, ints("after.active")), act
     assert np.array_equal(gen, ints("after.gen")), gen
+
+
+def rr_worked_problem():
+    """The scene of tests/golden/rr_worked_example.txt and its rows."""
+    rows = _rr_worked()
+    wp = np.array([[float(v) for v in seg.split()] for seg in rows["wp"].split("|")])
+    prob = scenes.Problem(
+        name="rr-worked", d=2, kind=scenes.KIND_TRANSLATE, dh=np.zeros((2, 4)),
+        sphere_link=np.zeros(1, dtype=np.int32), sphere=scenes.f32(np.array([[0.0, 0.0, 0.0, 0.05]])),
+        q_lo=scenes.f32(np.zeros(2)), q_hi=scenes.f32(np.ones(2)), q_start=scenes.f32([0.3, 0.5]),
+        q_goal=scenes.f32([0.8, 0.5]), t_min=scenes.f32(2.0), t_max=scenes.f32(10.0), v_max=scenes.f32(1.0),
+        n_wp=np.array([len(wp)], dtype=np.int32), wp=scenes.f32(wp[None]), obs_r=scenes.f32([0.08]),
+        params=scenes.Params(variant=scenes.VARIANT_RR, n_groups=4, batch=64, eta=0.1, h=0.01, dt=0.02,
+                             cap_fwd=1 << 10, cap_bwd=1 << 8, seed=1),
+        seed=0)
+    return prob, rows
 
 
 

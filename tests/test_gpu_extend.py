@@ -516,3 +516,19 @@ def test_iterate_equals_sample_and_extend(name, make):
             assert np.array_equal(ea[k][base:base + c], eb[k][base:base + c]), (k, p)
     ia, ib = ga.info(), gb.info()
     assert ia["U"] == ib["U"] and ia["C"] == ib["C"] and ia["iter"] == ib["iter"] == n
+
+
+def test_recycling_initial_roots_worked_example():
+    """The library's initial recycling roots on the hand-worked scene of
+    tests/golden/rr_worked_example.txt (reading 12) equal the values derived
+    by hand, as the oracle's do."""
+    from paper_2609_30533_amd.lib import Problem
+    from tests import oracle_pins
+    torch_cuda()
+    prob, rows = oracle_pins.rr_worked_problem()
+    gp = Problem(prob)
+    T, act, gen, k = gp.slots()
+    assert np.array_equal(k, [int(v) for v in rows["init.k"].split()]), k
+    assert np.allclose(T, [float(v) for v in rows["init.T"].split()], atol=1e-6), T
+    assert np.array_equal(act, [int(v) for v in rows["init.active"].split()]), act
+    assert np.array_equal(gen, [0, 0, 0, 0]), gen
