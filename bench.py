@@ -393,11 +393,16 @@ def batched_section(lib, args):
     tpath = os.path.join(ROOT, "paper_2609_30533_amd", "data", "tuning.json")
     table = autotune.load(tpath) if os.path.exists(tpath) else {}
     probs = [scenes.mixed(s) for s in range(args.batch_problems)]
+    for p in probs:
+        # one obstacle tile for the whole batch: the members' kernel instances
+        # then differ only by robot kind (two scene classes instead of six)
+        p.params.obstacle_tile = args.batch_obstacle_tile
     r = batched_run(lib, probs, args.batch_ms, table=table)
     fm = r["first_ms"][np.isfinite(r["first_ms"])]
     return {
         "batched_workload": "mixed seeds 0..%d: DOF 2/6/7, 4-64 obstacles, arrival widths 5-60 s, tree "
-                            "capacity 2^14-2^18, one batch, %.0f ms" % (args.batch_problems - 1, args.batch_ms),
+                            "capacity 2^14-2^18, one batch, %.0f ms, obstacle tile %s" % (
+                                args.batch_problems - 1, args.batch_ms, args.batch_obstacle_tile or "per problem"),
         "batched_edge_checks_per_s": r["edges"] / (r["total_ms"] * 1e-3),
         "batched_iterations": int(r["iterations"]),
         "batched_solved": int(r["n_solved"]),
@@ -710,6 +715,8 @@ def main():
     ap.add_argument("--queue-ms", type=float, default=100.0)
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
+    ap.add_argument("--batch-obstacle-tile", type=int, default=16,
+                    help="obstacle tile forced on every member of the heterogeneous batch (0: each its own)")
     ap.add_argument("--ttfs-lanes-bridge", type=int, default=32,
                     help="lanes per bridge chunk of every time-to-first-solution problem, plain and batched "
                          "(0: the library's default)")

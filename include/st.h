@@ -93,6 +93,10 @@ typedef struct st_params {
     uint32_t problem_id; /* Philox4x32-10 key word 1 */
     int32_t no_recycling;/* recycling variant: 1 keeps the initial roots, deactivation
                             only (the allocation ablation of Sec. VI); 0 recycles (Alg. 3) */
+    int32_t obstacle_tile;/* obstacles per register tile of the collision kernels: 0 picks 4, 8
+                            or 16 by the obstacle count; 4, 8 or 16 forces it (obstacles padded
+                            with far, zero-radius ones to a multiple of it; decisions unchanged).
+                            Problems of one batch that share a tile share kernel instances. */
 } st_params;
 
 /* Problem description (Sec. III): robot, configuration box C, start q_s,

@@ -128,6 +128,8 @@ static int validate(const st_problem_desc *D) {
     const st_params &P = D->params;
     if (P.variant != ST_INTERVAL_ROOT && P.variant != ST_ROOT_RECYCLING) return fail(ST_EINVAL, "variant %d", P.variant);
     if (P.no_recycling != 0 && P.no_recycling != 1) return fail(ST_EINVAL, "no_recycling %d", P.no_recycling);
+    if (P.obstacle_tile != 0 && P.obstacle_tile != 4 && P.obstacle_tile != 8 && P.obstacle_tile != 16)
+        return fail(ST_EINVAL, "obstacle_tile %d (0, 4, 8 or 16)", P.obstacle_tile);
     if (P.n_groups < 1 || P.n_groups > ST_MAX_GROUPS) return fail(ST_EINVAL, "n_groups %d", P.n_groups);
     if (P.batch < 1) return fail(ST_EINVAL, "batch %d", P.batch);
     if (!(P.eta > 0) || !(P.h > 0) || !(P.dt > 0) || !finite(P.eta) || !finite(P.h) || !finite(P.dt))
@@ -150,7 +152,7 @@ static int build_scene(st_problem *p, const st_problem_desc *D) {
     sc.kind = D->robot_kind == ST_ROBOT_DH ? kDH : kTranslate;
     sc.S = S;
     sc.O = O;
-    const int OT = ot_of(O);
+    const int OT = D->params.obstacle_tile > 0 ? D->params.obstacle_tile : ot_of(O);
     sc.O_pad = std::max(OT, (O + OT - 1) / OT * OT);
     sc.ot = OT;
     sc.v = (float)D->v_max;

@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("eta", C.c_double), ("h", C.c_double), ("dt", C.c_double),
                 ("p_new", C.c_double), ("p_guided", C.c_double),
                 ("cap_fwd", C.c_int32), ("cap_bwd", C.c_int32),
-                ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("no_recycling", C.c_int32)]
+                ("seed", C.c_uint32), ("problem_id", C.c_uint32), ("no_recycling", C.c_int32),
+                ("obstacle_tile", C.c_int32)]
 
 
 class Desc(C.Structure):
@@ -224,7 +225,7 @@ def make_desc(prob: scenes.Problem, problem_id: int = 0):
     p = prob.params
     D.params = Params(p.variant, p.n_groups, p.batch, p.eta, p.h, p.dt, p.p_new, p.p_guided, p.cap_fwd,
                       p.cap_bwd, p.seed & 0xFFFFFFFF, problem_id & 0xFFFFFFFF,
-                      1 if getattr(p, "no_recycling", 0) else 0)
+                      1 if getattr(p, "no_recycling", 0) else 0, int(getattr(p, "obstacle_tile", 0)))
     pairs = np.asarray(getattr(prob, "self_pairs", np.zeros((0, 2))), dtype=np.int32).reshape(-1, 2)
     boxes = np.asarray(getattr(prob, "boxes", np.zeros((0, 15))), dtype=np.float64).reshape(-1, 15)
     D.n_self_pairs = len(pairs)

@@ -65,6 +65,7 @@ class Params:
     cap_bwd: int = 1 << 14     # capacity of each backward pool (group or slot)
     seed: int = 1
     no_recycling: int = 0      # recycling variant: keep the initial roots (the paper's ablation)
+    obstacle_tile: int = 0     # collision kernels' obstacle tile: 0 automatic, or 4 / 8 / 16
 
 
 @dataclass

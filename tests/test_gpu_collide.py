@@ -107,6 +107,38 @@ def test_launch_shapes_do_not_change_results(oracle_lib, maker):
     assert np.array_equal(ref[0][ok].astype(bool), res["free"][ok].astype(bool))
 
 
+@pytest.mark.parametrize("maker", [lambda: scenes.disc2d(4), lambda: scenes.arm6(3, n_obs=5)], ids=["disc2d", "arm6-5obs"])
+def test_forced_obstacle_tile_pads_without_changing_results(maker):
+    """A problem created with a forced obstacle tile (its obstacles padded
+    with far, zero-radius ones) decides every state and edge as the same
+    problem with the automatic tile, and plans the same trees."""
+    from paper_2609_30533_amd.lib import Problem
+    torch = torch_cuda()
+    base = maker()
+    banner("forced obstacle tile %s" % base.name)
+    xa, xb = scenes.synthetic_edges(base, 3000, seed=13, bridge_mix=True)
+    da, db = to_dev(xa), to_dev(xb)
+    ref = None
+    for tile in (0, 4, 8, 16):
+        prob = maker()
+        prob.params.batch = 256
+        prob.params.obstacle_tile = tile
+        gp = Problem(prob)
+        f, h = gp.check_edges(da, db)
+        gp.iterate(6)
+        torch.cuda.synchronize()
+        ex = gp.export()
+        cur = (f.cpu().numpy(), h.cpu().numpy(), ex["counts"], gp.info()["obstacle_tile"])
+        if tile:
+            assert cur[3] == tile
+        if ref is None:
+            ref = cur
+            continue
+        assert np.array_equal(cur[0], ref[0]) and np.array_equal(cur[1], ref[1]), tile
+        assert np.array_equal(cur[2], ref[2]), tile
+        gp.close()
+
+
 def test_edges_degenerate_and_long(oracle_lib):
     """Zero-length edges, pure waits, edges leaving the box or the horizon,
     and long bridges that span thousands of states."""
