@@ -254,7 +254,7 @@ def ttfs_section(lib, args, validate):
     paper's evaluation: planner seeds 1-3, common-success sets, bootstrap
     intervals): the plain planner one problem at a time (B = 4096, the
     headline configuration) against the learned proposal with all problems
-    in one batch (B = 256 each, mixed 50/50), with two batched controls on
+    in one batch (--ttfs-batch-samples each, mixed 50/50), with two batched controls on
     the same batch: the plain sampler and an untrained network of the same
     architecture.  A batched problem's time is the device time from the
     batch's start to its first solution.  Solved paths go to `validate` (the
@@ -331,6 +331,9 @@ def ttfs_section(lib, args, validate):
         "ttfs_ms_mean_plain": mean(a), "ttfs_ms_mean_learned_batched": mean(b),
         "ttfs_bootstrap95_learned_batched_minus_plain": _bootstrap_median_diff(a, b),
         "ttfs_wilcoxon_p": _wilcoxon_p(a, b),
+        # direction of the paired comparison (the Wilcoxon test is two-sided)
+        "ttfs_pairs_learned_batched_faster": float(np.mean(np.asarray(b) < np.asarray(a))) if common else None,
+        "ttfs_median_paired_diff_ms": float(np.median(np.asarray(b) - np.asarray(a))) if common else None,
     })
     # controls on their own common sets with plain
     for c in ("plain_batched", "untrained_batched"):
