@@ -152,7 +152,6 @@ static int batch_build(st_batch *b) {
         L.mt_br = std::max(L.mt_br, a.mt_br);
         L.nb_worker = std::max<int>(L.nb_worker, (int)((B + 255) / 256));
         L.nb_edge = std::max(L.nb_edge, std::max(a.edge_ext.nb_edge, a.edge_br.nb_edge));
-        L.nb_merge = std::max<int>(L.nb_merge, (int)((B * 64 + 255) / 256));
         L.max_pools = std::max(L.max_pools, p->tree.n_pools);
         L.ext_flat = L.ext_flat && a.edge_ext.flat > 0;
         const std::vector<void *> sb = member_bufs(p);
@@ -186,6 +185,7 @@ static int batch_build(st_batch *b) {
             c.nb_items_ext = std::max(c.nb_items_ext, edge_ext[m].nb_items);
             c.nb_items_br = std::max(c.nb_items_br, edge_br[m].nb_items);
             if (edge_ext[m].flat > 0) c.nb_flat = std::max(c.nb_flat, flat_blocks(edge_ext[m].E, edge_ext[m].flat));
+            c.nb_bcheck = std::max<int>(c.nb_bcheck, (int)((b->mem[m]->prm.batch * 64 + 255) / 256));
             c.lds = std::max(c.lds, scene_lds_bytes(b->mem[m]->sc));
             c.lds_sample = std::max(c.lds_sample, sample_lds_bytes(b->mem[m], nullptr));
         }

@@ -300,9 +300,7 @@ __global__ __launch_bounds__(256) void k_sample(SampleArgs a0, const SampleArgs 
 // sampler does this itself): each worker's nearest-node set, its place in the
 // set's bucket, its empty key, and the snapshot of the batch.  One block; the
 // counters are overwritten.
-template <bool MULTI>
-__global__ __launch_bounds__(1024) void k_prep(PrepArgs a0, const PrepArgs *__restrict__ av) {
-    const PrepArgs &a = MULTI ? av[blockIdx.y] : a0;
+__global__ __launch_bounds__(1024) void k_prep(PrepArgs a) {
     __shared__ int cnt[kMaxPools];
     const int tid = threadIdx.x;
     for (int i = tid; i < a.n_pools; i += blockDim.x) cnt[i] = 0;
@@ -1705,7 +1703,7 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
     const int blocks = (int)((B + 255) / 256);
     prof_mark(p, kStNearest, s);
     if (!bucketed) {
-        k_prep<false><<<1, 1024, 0, s>>>(a.prep_nn, nullptr);
+        k_prep<<<1, 1024, 0, s>>>(a.prep_nn);
         ST_HIP(hipGetLastError());
     }
     if (p->prm.variant == ST_INTERVAL_ROOT)
@@ -1801,7 +1799,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     for (const BatchClass &c : L.classes) {
         dispatch_scene_edges(c.key, [&](auto kind, auto ot, auto obs) {
             k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, true>
-                <<<dim3(L.nb_merge, c.n), 256, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
+                <<<dim3(c.nb_bcheck, c.n), 256, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
         });
         ST_HIP(hipGetLastError());
     }

@@ -137,7 +137,7 @@ struct BatchClass {
     int split_ext, split_br;  // lanes per state (log2) of the two edge launches
     const int32_t *members; // device: record indices
     int n;                  // members
-    int nb_sample, nb_items_ext, nb_items_br, nb_flat;  // grid maxima over the members
+    int nb_sample, nb_items_ext, nb_items_br, nb_flat, nb_bcheck;  // grid maxima over the members
     size_t lds;             // dynamic LDS, maximum over the members
     size_t lds_sample;      // the sampler's (scene and guided windows), maximum over the members
 };
@@ -156,7 +156,7 @@ struct BatchLaunch {
     const RootsArgs *roots = nullptr;
     const int32_t *ir_members = nullptr, *rr_members = nullptr, *all_members = nullptr;
     int n_ir = 0, n_rr = 0;
-    int mt_nn = 0, mt_br = 0, nch = 1, nb_worker = 0, nb_edge = 0, nb_merge = 0, max_pools = 0;
+    int mt_nn = 0, mt_br = 0, nch = 1, nb_worker = 0, nb_edge = 0, max_pools = 0;
     bool ext_flat = true;  // every member's extension edges take the flattened path
     std::vector<BatchClass> classes;
 };
