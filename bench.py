@@ -193,6 +193,7 @@ def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_
     A member's first-solution time is resolved to the launch (graph of
     iters_per_launch iterations) that found it."""
     from paper_2609_30533_amd import autotune
+    t_setup = time.perf_counter()
     if table is not None:
         for p in probs:
             autotune.apply(p, table)
@@ -207,7 +208,10 @@ def batched_run(lib, probs, budget_ms, proposal=None, mix=0.5, table=None, keep_
         proposal.install(gps, probs, mix)
     b = lib.Batch(gps, iters_per_launch=iters_per_launch)
     w0 = [g.work_counters() for g in gps]
+    # host set-up of the batch (problems, start checks, proposal, graphs)
+    setup_ms = (time.perf_counter() - t_setup) * 1e3
     r = b.plan(max_ms=budget_ms)
+    r["setup_ms"] = setup_ms
     w1 = [g.work_counters() for g in gps]
     edges = sum((a["edges"] - z["edges"]) + (a["bridges"] - z["bridges"]) for a, z in zip(w1, w0))
     per = [(a["edge_states"] - z["edge_states"]) + (a["bridge_states"] - z["bridge_states"]) for a, z in zip(w1, w0)]
@@ -256,9 +260,12 @@ def ttfs_section(lib, args, validate):
     headline configuration) against the learned proposal with all problems
     in one batch (--ttfs-batch-samples each, mixed 50/50), with two batched controls on
     the same batch: the plain sampler and an untrained network of the same
-    architecture.  A batched problem's time is the device time from the
-    batch's start to its first solution.  Solved paths go to `validate` (the
-    oracle re-checks them in the CPU leg)."""
+    architecture.  Both sides are timed on the device from the first
+    iteration's launch to the end of the iteration that found a problem's
+    first solution (a batch member: from the batch's first launch); the
+    set-up before it (start checks, graph capture, proposal) is not counted
+    on either side.  Solved paths go to `validate` (the oracle re-checks them
+    in the CPU leg)."""
     from paper_2609_30533_amd import proposal
     wpath = os.path.join(ROOT, "paper_2609_30533_amd", "data", "proposal_arm6.npy")
     base = []
@@ -311,9 +318,11 @@ def ttfs_section(lib, args, validate):
     out = {
         "ttfs_workload": "arm6 evaluation seeds 0..%d with start and goal accepted by the library (%d problems), "
                          "planner seeds %s; plain = one problem at a time, B=4096, %.0f ms budget, stop at the "
-                         "first solution; batched = all problems in one batch, B=%d each, %.0f ms, first solutions timed "
-                         "to the iteration; learned and untrained networks mixed 50/50; %s lanes per bridge "
-                         "chunk in both" % (
+                         "first solution; batched = all problems in one batch, B=%d each, %.0f ms; learned and "
+                         "untrained networks mixed 50/50; %s lanes per bridge chunk in both; a time is device "
+                         "time from the first iteration's launch to the end of the iteration that found the "
+                         "first solution, the set-up (start check, graph capture, proposal) excluded on both "
+                         "sides" % (
                              args.ttfs_problems - 1, n, list(args.planner_seeds), args.ttfs_single_ms,
                              args.ttfs_batch_samples, args.ttfs_ms, args.ttfs_lanes_bridge or "default"),
         "ttfs_problems": n,
@@ -365,25 +374,32 @@ def ttfs_section(lib, args, validate):
         for i in range(Q):
             p = _with(base[i][1], 4096, 1 << 18, 1 << 16, 1)
             g = lib.Problem(p)
-            ts = (time.perf_counter() - t0) * 1e3
             r = g.plan(max_ms=args.queue_ms, stop_at_first=True, iters_per_sync=1)
             if r["first_iter"] >= 0:
-                queue[i] = ts + r["first_ms"]
+                # host time at the return of the first solution (with its path)
+                queue[i] = (time.perf_counter() - t0) * 1e3
             g.close()
         plain_queue_wall = (time.perf_counter() - t0) * 1e3
+        # the batch's set-up (problems, start checks, proposal, graphs) counts
+        # too: a member's time is the set-up plus the device time to its first
+        # solution
         lq = batched_run(lib, [_with(base[i][1], args.ttfs_batch_samples, 1 << 16, 1 << 13, 1) for i in range(Q)],
                          args.queue_ms, proposal=trained, iters_per_launch=1)
-        qcommon = [i for i in queue if math.isfinite(lq["first_ms"][i])]
+        lq_first = lq["setup_ms"] + lq["first_ms"]
+        qcommon = [i for i in queue if math.isfinite(lq_first[i])]
         out.update({
             "queue_workload": "the first %d evaluation problems submitted at once; %.0f ms budget per problem "
                               "(plain, one after another) or for the whole batch (learned+batched); time from "
-                              "submission to each problem's first solution, median over problems both solve" % (
-                                  Q, args.queue_ms),
+                              "submission to each problem's first solution, every set-up included (plain: host "
+                              "time at the return of its first solution; batched: the batch's host set-up plus "
+                              "the device time to the member's first solution), median over problems both "
+                              "solve" % (Q, args.queue_ms),
             "queue_ms_median_plain": med([queue[i] for i in qcommon]),
-            "queue_ms_median_learned_batched": med([float(lq["first_ms"][i]) for i in qcommon]),
+            "queue_ms_median_learned_batched": med([float(lq_first[i]) for i in qcommon]),
             "queue_common": len(qcommon),
             "queue_wall_ms_plain": plain_queue_wall,
-            "queue_wall_ms_learned_batched": float(lq["total_ms"]),
+            "queue_setup_ms_learned_batched": float(lq["setup_ms"]),
+            "queue_wall_ms_learned_batched": float(lq["setup_ms"] + lq["total_ms"]),
         })
     return out
 

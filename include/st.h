@@ -176,8 +176,11 @@ typedef struct st_path {
     double length;           /* C: configuration path length */
     int64_t iterations;
     int64_t first_solution_iter;
-    double first_solution_ms;/* wall time from the start of st_plan to the first incumbent */
-    double total_ms;
+    double first_solution_ms;/* device time from the first iteration's launch to the end of the launches
+                                (iters_per_sync iterations) that found the first incumbent; the start
+                                check and the launch set-up (buffers, graph capture) come before it and
+                                are not counted.  st_plan_sequence: the sum over its legs */
+    double total_ms;         /* wall time of the call, set-up included */
 } st_path;
 
 /* Snapshot of the planner state (host). */

@@ -751,6 +751,7 @@ int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals
     std::vector<double> states;  // absolute-time path, rows of d + 1
     double T = 0.0, C = 0.0;
     int64_t iters = 0;
+    double first_ms = 0.0;
     int rc = ST_OK;
     SequenceLeg L;
     for (int i = 0; i < m && rc == ST_OK; ++i) {
@@ -777,9 +778,10 @@ int st_plan_sequence(const st_problem_desc *desc, int32_t m, const double *goals
         T += leg.arrival;
         C += leg.length;
         iters += leg.iterations;
+        first_ms += leg.first_solution_ms;
         if (i + 1 == m) {
             out->first_solution_iter = leg.first_solution_iter;
-            out->first_solution_ms = ms_since() - (leg.total_ms - leg.first_solution_ms);
+            out->first_solution_ms = first_ms;
         }
         st_path_free(&leg);
         qs.assign(goals + (size_t)i * d, goals + (size_t)(i + 1) * d);

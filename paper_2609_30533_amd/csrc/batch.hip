@@ -111,7 +111,9 @@ static int batch_build(st_batch *b) {
     int64_t tiles = 0;
     for (st_problem *p : b->mem) tiles += (p->prm.batch + 255) / 256 + 2;
     const int nch = (int)std::min<int64_t>(64, std::max<int64_t>(8, 8192 / std::max<int64_t>(tiles, 1)));
-    const int min_items = std::max(1, 1024 / P);
+    // item blocks per member: about 4096 over the batch, at least four each,
+    // so that a member whose bridges are long spreads them over many waves
+    const int min_items = std::max(4, 4096 / P);
     int64_t all_edges = 0;
     for (st_problem *p : b->mem) all_edges += p->prm.batch;
     std::vector<SampleArgs> smp(P);
@@ -153,6 +155,7 @@ static int batch_build(st_batch *b) {
         L.nb_worker = std::max<int>(L.nb_worker, (int)((B + 255) / 256));
         L.nb_edge = std::max(L.nb_edge, std::max(a.edge_ext.nb_edge, a.edge_br.nb_edge));
         L.max_pools = std::max(L.max_pools, p->tree.n_pools);
+        L.ins_threads = std::max(L.ins_threads, insert_threads(B));
         L.ext_flat = L.ext_flat && a.edge_ext.flat > 0;
         const std::vector<void *> sb = member_bufs(p);
         b->saved_bufs.insert(b->saved_bufs.end(), sb.begin(), sb.end());
@@ -185,7 +188,7 @@ static int batch_build(st_batch *b) {
             c.nb_items_ext = std::max(c.nb_items_ext, edge_ext[m].nb_items);
             c.nb_items_br = std::max(c.nb_items_br, edge_br[m].nb_items);
             if (edge_ext[m].flat > 0) c.nb_flat = std::max(c.nb_flat, flat_blocks(edge_ext[m].E, edge_ext[m].flat));
-            c.nb_bcheck = std::max<int>(c.nb_bcheck, (int)((b->mem[m]->prm.batch * 64 + 255) / 256));
+            c.nb_bcheck = std::max<int>(c.nb_bcheck, (int)b->mem[m]->prm.batch);  // one wave each
             c.lds = std::max(c.lds, scene_lds_bytes(b->mem[m]->sc));
             c.lds_sample = std::max(c.lds_sample, sample_lds_bytes(b->mem[m], nullptr));
         }

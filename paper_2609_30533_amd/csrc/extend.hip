@@ -747,7 +747,8 @@ __global__ __launch_bounds__(1024) void k_insert(InsertArgs a0, const InsertArgs
     if (tid == 0) s_last = 0;
     if (tid < 2) s_bcnt[tid] = 0;
     // the nearest-node buckets are consumed: empty for the next batch
-    if (p == 0 && tid < a.tree.n_pools) k.bcnt[tid] = 0;
+    if (p == 0)
+        for (int i = tid; i < a.tree.n_pools; i += blockDim.x) k.bcnt[i] = 0;
     // R consecutive workers per thread and pass; all their loads are issued
     // before any store
     constexpr int R = 4;
@@ -1730,7 +1731,7 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
         ST_HIP(launch_edge_args(a.edge_ext, s));
     }
     prof_mark(p, kStInsert, s);
-    k_insert<false><<<p->tree.n_pools, 1024, 0, s>>>(a.insert, nullptr);
+    k_insert<false><<<p->tree.n_pools, insert_threads(B), 0, s>>>(a.insert, nullptr);
     ST_HIP(hipGetLastError());
     prof_mark(p, kStBridgeSel, s);
     k_scan<kScanBridge, false><<<dim3(a.mt_br, a.scan_br.nch), kTileQ, 0, s>>>(a.scan_br, nullptr, nullptr);
@@ -1792,14 +1793,16 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
             ST_HIP(launch_edge_items_multi(c.key, c.split_ext, L.edge_ext, c.members, c.n, c.nb_items_ext, c.lds, s));
         ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
     }
-    k_insert<true><<<dim3(L.max_pools, L.P), 1024, 0, s>>>(InsertArgs{}, L.insert);
+    k_insert<true><<<dim3(L.max_pools, L.P), L.ins_threads, 0, s>>>(InsertArgs{}, L.insert);
     k_scan<kScanBridge, true><<<dim3(L.mt_br, L.nch, L.P), kTileQ, 0, s>>>(ScanArgs{}, L.scan_br, L.all_members);
     // the merge and the first 64 states of every bridge edge, per scene
-    // class, then the item kernel for the undecided rest
+    // class, then the item kernel for the undecided rest; one wave per block
+    // (a member's blocks past its advanced workers leave before staging, and
+    // a checking wave does not wait for three others to be scheduled)
     for (const BatchClass &c : L.classes) {
         dispatch_scene_edges(c.key, [&](auto kind, auto ot, auto obs) {
             k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, true>
-                <<<dim3(c.nb_bcheck, c.n), 256, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
+                <<<dim3(c.nb_bcheck, c.n), 64, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
         });
         ST_HIP(hipGetLastError());
     }
@@ -1906,7 +1909,10 @@ static int capture_iterations(st_problem *p, int n, hipGraphExec_t *out) {
 
 constexpr int kGraphChunk = 4;
 
-static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
+// Launch set-up of the planner's iterations: work and edge buffers for the
+// problem's samples per iteration and (graph replays) the graphs of one and of
+// kGraphChunk iterations.  Synchronous; a no-op once done.
+static int iterate_prepare(st_problem *p) {
     const int64_t B = p->prm.batch;
     int rc = work_reserve(p, B);
     if (rc != ST_OK) return rc;
@@ -1914,6 +1920,21 @@ static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
         graphs_free(p);
         if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
     }
+    if (p->prof || !p->use_graphs) return ST_OK;
+    if (p->graph_B != B || !p->graph[0] || !p->graph[1]) {
+        graphs_free(p);
+        ST_HIP(hipDeviceSynchronize());
+        if ((rc = capture_iterations(p, 1, &p->graph[0])) != ST_OK) return rc;
+        if ((rc = capture_iterations(p, kGraphChunk, &p->graph[1])) != ST_OK) return rc;
+        p->graph_B = B;
+    }
+    return ST_OK;
+}
+
+static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
+    const int64_t B = p->prm.batch;
+    int rc = iterate_prepare(p);
+    if (rc != ST_OK) return rc;
     if (p->prof || !p->use_graphs) {
         // eager launches (stage timing records events between kernels)
         const st_samples smp = work_samples(p);
@@ -1923,13 +1944,6 @@ static int iterate(st_problem *p, int64_t iters, hipStream_t s) {
             p->iter++;
         }
         return ST_OK;
-    }
-    if (p->graph_B != B || !p->graph[0] || !p->graph[1]) {
-        graphs_free(p);
-        ST_HIP(hipDeviceSynchronize());
-        if ((rc = capture_iterations(p, 1, &p->graph[0])) != ST_OK) return rc;
-        if ((rc = capture_iterations(p, kGraphChunk, &p->graph[1])) != ST_OK) return rc;
-        p->graph_B = B;
     }
     int64_t left = iters;
     while (left >= kGraphChunk) {
@@ -2141,16 +2155,26 @@ int st_plan(st_problem *p, const st_budget *b, st_path *out) {
     ST_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     PlanDev *host = nullptr;
     ST_HIP(hipHostMalloc((void **)&host, sizeof(PlanDev), hipHostMallocDefault));
+    // the launch set-up (buffers, graph capture) before the first solution's
+    // clock, which then runs on the device: from an event ahead of the first
+    // launch to one behind the launches that found the solution
+    int rc = iterate_prepare(p);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    if (rc == ST_OK && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
+                        hipEventRecord(ev[0], s) != hipSuccess)) {
+        set_error("st_plan: event set-up failed");
+        rc = ST_EHIP;
+    }
     const int chunk = b->iters_per_sync > 0 ? b->iters_per_sync : 8;
     int64_t done_iters = 0;
-    int rc = ST_OK;
-    while (true) {
+    while (rc == ST_OK) {
         int64_t n = chunk;
         if (b->max_iters > 0) n = std::min<int64_t>(n, b->max_iters - done_iters);
         if (n <= 0) break;
         if ((rc = iterate(p, n, s)) != ST_OK) break;
         done_iters += n;
-        if (hipMemcpyAsync(host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (hipEventRecord(ev[1], s) != hipSuccess ||
+            hipMemcpyAsync(host, p->d_plan, sizeof(PlanDev), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess) {
             set_error("st_plan: device synchronisation failed");
             rc = ST_EHIP;
@@ -2158,7 +2182,13 @@ int st_plan(st_problem *p, const st_budget *b, st_path *out) {
         }
         if (host->first_iter >= 0 && out->first_solution_iter < 0) {
             out->first_solution_iter = host->first_iter;
-            out->first_solution_ms = ms_since();
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, ev[0], ev[1]) != hipSuccess) {
+                set_error("st_plan: event timing failed");
+                rc = ST_EHIP;
+                break;
+            }
+            out->first_solution_ms = t;
         }
         if (host->done) break;
         if (b->stop_at_first && host->first_iter >= 0) break;
@@ -2166,6 +2196,8 @@ int st_plan(st_problem *p, const st_budget *b, st_path *out) {
         if (b->max_iters <= 0 && b->max_ms <= 0 && !b->stop_at_first) break;
     }
     if (rc == ST_OK) rc = fetch_path(p, s, out);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     (void)hipHostFree(host);
     (void)hipStreamDestroy(s);
     out->total_ms = ms_since();

@@ -228,6 +228,12 @@ inline int split_for(int setting, int64_t E) {
     if (setting >= 0) return setting;
     return E <= 256 ? 2 : 0;
 }
+// Threads of an insertion block (one block per pool, four workers per thread
+// and pass): whole waves, enough for one pass over B workers, at most 1024.
+inline int insert_threads(int64_t B) {
+    const int64_t t = ((B + 3) / 4 + 63) / 64 * 64;
+    return (int)(t < 64 ? 64 : (t > 1024 ? 1024 : t));
+}
 // Record of one edge launch; the item kernel gets at least min_item_blocks blocks.
 EdgeArgs edge_args(const SceneDev &sc, const EdgeBufs &eb, int64_t E, const float *xa, const float *xb,
                    const uint8_t *valid, uint8_t *free_out, int32_t *first_hit, int lpe_shift,
