@@ -128,6 +128,10 @@ static int batch_build(st_batch *b) {
     std::map<std::tuple<int, int, int, int, int>, std::vector<int32_t>> cls;
     std::vector<PlanDev *> pls(P);
     L.nch = nch;
+    // one-wave scan blocks when every member draws at most 64 samples
+    int64_t B_max = 0;
+    for (st_problem *p : b->mem) B_max = std::max<int64_t>(B_max, p->prm.batch);
+    L.scan_tq = B_max <= 64 ? 64 : 256;
     for (int m = 0; m < P; ++m) {
         st_problem *p = b->mem[m];
         const int64_t B = p->prm.batch;
@@ -150,8 +154,13 @@ static int batch_build(st_batch *b) {
         cls[std::make_tuple(p->sc.stat ? (int)kDHStatic : p->sc.kind, p->sc.ot, p->sc.obs_mode, a.edge_ext.split_shift,
                             a.edge_br.split_shift)]
             .push_back(m);
-        L.mt_nn = std::max(L.mt_nn, a.mt_nn);
-        L.mt_br = std::max(L.mt_br, a.mt_br);
+        // query tiles of the scans (tiles of L.scan_tq queries: one per node
+        // set and a full one per L.scan_tq samples at most); the two
+        // nearest-node launches each over their own members
+        const int tiles_b = (int)((B + L.scan_tq - 1) / L.scan_tq);
+        int &mt = p->prm.variant == ST_INTERVAL_ROOT ? L.mt_nn_ir : L.mt_nn_rr;
+        mt = std::max(mt, tiles_b + p->tree.n_pools);
+        L.mt_br = std::max(L.mt_br, tiles_b + 2);
         L.nb_worker = std::max<int>(L.nb_worker, (int)((B + 255) / 256));
         L.nb_edge = std::max(L.nb_edge, std::max(a.edge_ext.nb_edge, a.edge_br.nb_edge));
         L.max_pools = std::max(L.max_pools, p->tree.n_pools);

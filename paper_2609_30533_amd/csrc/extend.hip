@@ -359,17 +359,20 @@ enum { kScanRho = 0, kScanConfig = 1, kScanBridge = 2 };
 constexpr int kMinSliceNodes = 64;  // nearest-node scans: nodes per slice at least
 
 
-// One block = one tile of up to 256 queries (one per thread) against the
+// One block = one tile of up to TQ queries (one per thread) against the
 // y-th of nch slices of its node set.  The set is a single pool or the
 // concatenation of the backward pools; nodes stream through LDS in rounds of
-// 256 (each thread loads one node, coalesced per SoA row), and the next
-// round is fetched into registers while the current one is scanned.
-template <int MODE, bool MULTI>
-__global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__restrict__ av,
-                                                 const int32_t *__restrict__ members) {
-    __shared__ __align__(16) float sx[kTileQ][8];
-    __shared__ float sT[kTileQ];
-    __shared__ int32_t sI[kTileQ];
+// TQ (each thread loads one node, coalesced per SoA row), and the next round
+// is fetched into registers while the current one is scanned.  TQ is 256, or
+// 64 for a batch of problems with at most 64 samples each: their tiles hold a
+// few queries, and one-wave blocks keep four times as many of the launch's
+// (mostly empty) blocks in flight.
+template <int MODE, bool MULTI, int TQ = kTileQ>
+__global__ __launch_bounds__(TQ) void k_scan(ScanArgs a0, const ScanArgs *__restrict__ av,
+                                             const int32_t *__restrict__ members) {
+    __shared__ __align__(16) float sx[TQ][8];
+    __shared__ float sT[TQ];
+    __shared__ int32_t sI[TQ];
     __shared__ int32_t s_pool[kMaxPools + 1], s_pre[kMaxPools + 1], s_cnt[kMaxPools + 1];
     __shared__ int32_t s_np;
     const ScanArgs &a = MULTI ? av[members[blockIdx.z]] : a0;
@@ -388,11 +391,12 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__
         // from the counts (read together, then walked from LDS by every thread)
         __shared__ int32_t s_bc[kMaxPools];
         const int nsets = a.bmode == 1 ? a.tree.n_pools : 2;
-        if (tid < nsets) s_bc[tid] = a.bcnt[tid];
+        // (a block of 64 threads may have fewer threads than sets)
+        for (int i = tid; i < nsets; i += TQ) s_bc[i] = a.bcnt[i];
         __syncthreads();
         int acc = 0, sb = 0, kt = -1;
         for (; sb < nsets; ++sb) {
-            const int nt = (s_bc[sb] + kTileQ - 1) / kTileQ;
+            const int nt = (s_bc[sb] + TQ - 1) / TQ;
             if (t < acc + nt) {
                 kt = t - acc;
                 break;
@@ -411,7 +415,7 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__
             set_id = sb == 0 ? kSetAllBackward : 0;
             sg = sb == 0 ? -1 : 1;
         }
-        tile = make_int4(set_id, kt * kTileQ, min(kTileQ, s_bc[sb] - kt * kTileQ), sg);
+        tile = make_int4(set_id, kt * TQ, min(TQ, s_bc[sb] - kt * TQ), sg);
         qrow = (int64_t)sb * a.bstride;
     }
     const int set = tile.x, n = tile.z;
@@ -456,7 +460,7 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__
     // two, at most a wave); lane `sub` of a query takes every L-th node of a
     // round, and the query's L lanes combine their bests at the end
     int lq_shift = 0;
-    while (lq_shift < 6 && n * (2 << lq_shift) <= kTileQ) ++lq_shift;
+    while (lq_shift < 6 && n * (2 << lq_shift) <= TQ) ++lq_shift;
     const int L = 1 << lq_shift, qs = tid >> lq_shift, sub = tid & (L - 1);
     const bool act = qs < n;
     const int q = act ? (qrow >= 0 ? a.border[qrow + tile.y + qs] : tile.y + qs) : 0;
@@ -496,15 +500,15 @@ __global__ __launch_bounds__(kTileQ) void k_scan(ScanArgs a0, const ScanArgs *__
         }
     };
     if (c0 < c1) fetch(c0);
-    for (int64_t c = c0; c < c1; c += kTileQ) {
+    for (int64_t c = c0; c < c1; c += TQ) {
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 8; ++j) sx[tid][j] = rx[j];
         sT[tid] = rT;
         sI[tid] = rI;
         __syncthreads();
-        if (c + kTileQ < c1) fetch(c + kTileQ);
-        const int m = (int)min<int64_t>(kTileQ, c1 - c);
+        if (c + TQ < c1) fetch(c + TQ);
+        const int m = (int)min<int64_t>(TQ, c1 - c);
         if (act) {
             // a node is two 16-byte broadcast reads (all eight slots, the
             // unused ones ignored); unrolled so that the reads of several
@@ -1771,11 +1775,16 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
         });
     }
     ST_HIP(hipGetLastError());
-    if (L.n_ir > 0)
-        k_scan<kScanRho, true><<<dim3(L.mt_nn, L.nch, L.n_ir), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.ir_members);
-    if (L.n_rr > 0)
-        k_scan<kScanConfig, true>
-            <<<dim3(L.mt_nn, L.nch, L.n_rr), kTileQ, 0, s>>>(ScanArgs{}, L.scan_nn, L.rr_members);
+    auto scan_multi = [&](auto mode, auto tq, int mt, int n, const int32_t *members, const ScanArgs *args) {
+        k_scan<decltype(mode)::value, true, decltype(tq)::value>
+            <<<dim3(mt, L.nch, n), decltype(tq)::value, 0, s>>>(ScanArgs{}, args, members);
+    };
+    auto scan_launch = [&](auto mode, int mt, int n, const int32_t *members, const ScanArgs *args) {
+        if (L.scan_tq == 64) scan_multi(mode, IC<64>{}, mt, n, members, args);
+        else scan_multi(mode, IC<kTileQ>{}, mt, n, members, args);
+    };
+    if (L.n_ir > 0) scan_launch(IC<kScanRho>{}, L.mt_nn_ir, L.n_ir, L.ir_members, L.scan_nn);
+    if (L.n_rr > 0) scan_launch(IC<kScanConfig>{}, L.mt_nn_rr, L.n_rr, L.rr_members, L.scan_nn);
     if (L.ext_flat) {
         // steering inside the flattened extension check, per scene class
         for (const BatchClass &c : L.classes) {
@@ -1794,7 +1803,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
         ST_HIP(launch_edge_finish_multi(L.edge_ext, L.P, L.nb_edge, s));
     }
     k_insert<true><<<dim3(L.max_pools, L.P), L.ins_threads, 0, s>>>(InsertArgs{}, L.insert);
-    k_scan<kScanBridge, true><<<dim3(L.mt_br, L.nch, L.P), kTileQ, 0, s>>>(ScanArgs{}, L.scan_br, L.all_members);
+    scan_launch(IC<kScanBridge>{}, L.mt_br, L.P, L.all_members, L.scan_br);
     // the merge and the first 64 states of every bridge edge, per scene
     // class, then the item kernel for the undecided rest; one wave per block
     // (a member's blocks past its advanced workers leave before staging, and

@@ -156,8 +156,9 @@ struct BatchLaunch {
     const RootsArgs *roots = nullptr;
     const int32_t *ir_members = nullptr, *rr_members = nullptr, *all_members = nullptr;
     int n_ir = 0, n_rr = 0;
-    int mt_nn = 0, mt_br = 0, nch = 1, nb_worker = 0, nb_edge = 0, max_pools = 0;
+    int mt_nn_ir = 0, mt_nn_rr = 0, mt_br = 0, nch = 1, nb_worker = 0, nb_edge = 0, max_pools = 0;
     int ins_threads = 64;  // insertion block size for the largest member
+    int scan_tq = 256;     // queries per scan tile and scan block size (256 or 64)
     bool ext_flat = true;  // every member's extension edges take the flattened path
     std::vector<BatchClass> classes;
 };

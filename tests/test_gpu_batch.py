@@ -35,6 +35,9 @@ def _members():
         _shrink(scenes.disc2d(2, params=scenes.Params(variant=1, n_groups=8)), 128, 1 << 14, 1 << 11),
         _shrink(scenes.arm7rr(2, n_obs=8), 320, 1 << 15, 1 << 11, groups=16),
         _shrink(scenes.arm6static(7), 256, 1 << 15, 1 << 12),
+        # 65 pools for 64 samples: the insertion blocks of the single runs
+        # have fewer threads than pools
+        _shrink(scenes.arm7rr(11, n_obs=8), 64, 1 << 14, 1 << 10, groups=64),
     ]
     for s in range(3):
         m = scenes.mixed(100 + s)
@@ -58,10 +61,22 @@ def _state(gp):
 
 
 def test_batch_equals_single_runs(oracle_lib):
+    _batch_vs_single(oracle_lib, _members(), "batch parity")
+
+
+def test_small_sample_batch_equals_single_runs(oracle_lib):
+    # at most 64 samples per member: the batch scans in tiles of 64 queries
+    # (one-wave blocks) while the single runs keep tiles of 256
+    probs = _members()
+    for i, p in enumerate(probs):
+        p.params.batch = (32, 48, 64)[i % 3]
+    _batch_vs_single(oracle_lib, probs, "small-sample batch parity")
+
+
+def _batch_vs_single(oracle_lib, probs, what):
     from paper_2609_30533_amd.lib import Batch, Problem
     torch = torch_cuda()
-    probs = _members()
-    banner("batch parity: %d members" % len(probs))
+    banner("%s: %d members" % (what, len(probs)))
     single = [Problem(p, problem_id=i) for i, p in enumerate(probs)]
     mem = [Problem(p, problem_id=i) for i, p in enumerate(probs)]
     batch = Batch(mem, iters_per_launch=4)
