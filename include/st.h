@@ -357,13 +357,14 @@ int st_path_get(st_problem *p, st_path *out);
 /* A batch runs one iteration of every member problem as one launch sequence:
  * each kernel of the pipeline is launched once for all members (once per
  * scene class for the two kernels specialised by robot kind, obstacle tile
- * and obstacle-time mode), blockIdx.y selecting the member; `iters_per_launch`
+ * and obstacle-time mode), one grid dimension selecting the member; `iters_per_launch`
  * iterations are captured in one HIP graph.  The batch borrows the handles:
  * they must outlive it and must not be iterated on their own while it exists.
  * Each member keeps its own parameters (samples per iteration, launch shapes
  * from st_set_tuning); changing them after st_batch_create has no effect on
  * the batch.  Members whose start state collides, or that are trivial, take no
- * part in the launches.  Synchronous. */
+ * part in the launches.  A member may draw at most 65535 samples per iteration
+ * (ST_EINVAL otherwise).  Synchronous. */
 typedef struct st_batch st_batch;
 int st_batch_create(st_problem *const *problems, int32_t n, int32_t iters_per_launch, st_batch **out);
 void st_batch_destroy(st_batch *b);

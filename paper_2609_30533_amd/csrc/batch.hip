@@ -265,6 +265,13 @@ int st_batch_create(st_problem *const *problems, int32_t n, int32_t iters_per_la
             set_error("st_batch_create: problem %d is null or repeated", i);
             return ST_EINVAL;
         }
+        // a member's samples index the second grid dimension of the batched
+        // bridge check (one block each)
+        if (problems[i]->prm.batch > kBatchMaxSamples) {
+            set_error("st_batch_create: problem %d draws %d samples per iteration (at most %d in a batch)", i,
+                      (int)problems[i]->prm.batch, kBatchMaxSamples);
+            return ST_EINVAL;
+        }
     }
     st_batch *b = new (std::nothrow) st_batch();
     if (!b) {

@@ -353,9 +353,11 @@ __global__ __launch_bounds__(256) void k_edge_items(EdgeArgs a) {
 
 __global__ __launch_bounds__(256) void k_edge_finish(EdgeArgs a) { edge_finish_body(a, blockIdx.x); }
 
-// Many problems per launch: blockIdx.y selects the problem's record (through
-// `members` for the per-scene-class item kernel); blocks past the problem's
-// own grid leave at once.
+// Many problems per launch: blockIdx.y selects the problem's record; the
+// per-scene-class item kernel takes its member from blockIdx.x (through
+// `members`; members vary fastest, so every member's first blocks, the ones
+// that hold its items, are dispatched before the members' empty blocks).
+// Blocks past the problem's own grid leave at once.
 __global__ __launch_bounds__(256) void k_edge_plan_multi(const EdgeArgs *__restrict__ av) {
     const EdgeArgs &a = av[blockIdx.y];
     if ((int)blockIdx.x >= a.nb_edge) return;
@@ -366,9 +368,9 @@ template <int KIND, int OT, int OBS, int SPLIT>
 __global__ __launch_bounds__(256) void k_edge_items_multi(const EdgeArgs *__restrict__ av,
                                                           const int32_t *__restrict__ members) {
     extern __shared__ float4 lds[];
-    const EdgeArgs &a = av[members[blockIdx.y]];
-    if ((int)blockIdx.x >= a.nb_items) return;
-    edge_items_body<KIND, OT, OBS, SPLIT>(a, lds, blockIdx.x, a.nb_items);
+    const EdgeArgs &a = av[members[blockIdx.x]];
+    if ((int)blockIdx.y >= a.nb_items) return;
+    edge_items_body<KIND, OT, OBS, SPLIT>(a, lds, blockIdx.y, a.nb_items);
 }
 
 __global__ __launch_bounds__(256) void k_edge_finish_multi(const EdgeArgs *__restrict__ av) {
@@ -540,7 +542,7 @@ hipError_t launch_edge_items_multi(const SceneDev &cls, int split_shift, const E
                                    hipStream_t s) {
     dispatch_split(cls, split_shift, [&](auto kind, auto ot, auto obs, auto split) {
         k_edge_items_multi<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, decltype(split)::value>
-            <<<dim3(max_nb_items, n_members), dim3(256), lds, s>>>(d_args, d_members);
+            <<<dim3(n_members, max_nb_items), dim3(256), lds, s>>>(d_args, d_members);
     });
     return hipGetLastError();
 }

@@ -918,13 +918,17 @@ __global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a0, EdgeArgs ea
                                                       const EdgeArgs *__restrict__ ev,
                                                       const int32_t *__restrict__ members) {
     extern __shared__ float4 lds[];
-    const int mi = MULTI ? members[blockIdx.y] : 0;
+    // many problems per launch: the member is blockIdx.x, so that members
+    // vary fastest and every member's first blocks (the ones that check) are
+    // dispatched ahead of the members' empty blocks; blocks past the
+    // member's own grid leave
+    const int bx = MULTI ? (int)blockIdx.y : (int)blockIdx.x;
+    const int mi = MULTI ? members[blockIdx.x] : 0;
     const BridgeArgs &a = MULTI ? av[mi] : a0;
     const EdgeArgs &ea = MULTI ? ev[mi] : ea0;
-    // many problems per launch: blocks past this problem's own grid leave
-    if (MULTI && (int64_t)blockIdx.x * (blockDim.x >> 6) >= a.B) return;
+    if (MULTI && (int64_t)bx * (blockDim.x >> 6) >= a.B) return;
     const int lane = threadIdx.x & 63;
-    const int64_t i = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t i = ((int64_t)bx * blockDim.x + threadIdx.x) >> 6;
     const Work &k = a.w;
     const SceneDev &sc = ea.sc;
     const EdgeBufs &eb = ea.eb;
@@ -939,7 +943,7 @@ __global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a0, EdgeArgs ea
     const int32_t nb0 = k.bcnt[kBcntBridge], nb1 = k.bcnt[kBcntBridge + 1];
     const int64_t nsel = (int64_t)nb0 + nb1;
     // a block past the advanced workers has nothing more to do (whole block)
-    if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= nsel) return;
+    if ((int64_t)bx * (blockDim.x >> 6) >= nsel) return;
     const bool in = i < nsel;
     const int64_t w = in ? (i < nb0 ? k.border_br[i] : k.border_br[a.B + (i - nb0)]) : 0;
     unsigned long long bk = kNoKey;
@@ -1811,7 +1815,7 @@ int launch_batch_iteration(const BatchLaunch &L, hipStream_t s) {
     for (const BatchClass &c : L.classes) {
         dispatch_scene_edges(c.key, [&](auto kind, auto ot, auto obs) {
             k_bridge_check<decltype(kind)::value, decltype(ot)::value, decltype(obs)::value, true>
-                <<<dim3(c.nb_bcheck, c.n), 64, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
+                <<<dim3(c.n, c.nb_bcheck), 64, c.lds, s>>>(BridgeArgs{}, EdgeArgs{}, L.merge, L.edge_br, c.members);
         });
         ST_HIP(hipGetLastError());
     }

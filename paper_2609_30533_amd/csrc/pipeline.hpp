@@ -142,6 +142,9 @@ struct BatchClass {
     size_t lds_sample;      // the sampler's (scene and guided windows), maximum over the members
 };
 
+// Samples per iteration of a batch member at most (a grid dimension).
+constexpr int kBatchMaxSamples = 65535;
+
 // Device arrays of records (P problems) and grid maxima for one iteration of
 // every problem of a batch.
 struct BatchLaunch {

@@ -292,3 +292,14 @@ def test_autotuner_table_is_honoured(tmp_path):
             # at most one extension edge per worker and iteration
             assert g.work_counters()["edges"] - e0 <= 4 * table[key]["samples"]
         b.close()
+
+
+def test_batch_rejects_too_many_samples():
+    from paper_2609_30533_amd.lib import Batch, Problem, StError
+    torch_cuda()
+    # a member's samples index a grid dimension of the batched bridge check
+    p = _shrink(scenes.disc2d(0), 65536, 1 << 12, 1 << 10)
+    gp = Problem(p)
+    with pytest.raises(StError, match="samples per iteration"):
+        Batch([gp])
+    gp.close()
