@@ -142,6 +142,9 @@ static int batch_build(st_batch *b) {
         scan_nn[m] = a.scan_nn;
         scan_br[m] = a.scan_br;
         steer[m] = a.steer;
+        // the batch's extension launch: the most edges per block (fewer, fuller
+        // blocks for its many members)
+        if (a.edge_ext.flat > 0) a.edge_ext.flat = kFlatEdges;
         edge_ext[m] = a.edge_ext;
         edge_br[m] = a.edge_br;
         ins[m] = a.insert;
