@@ -1707,7 +1707,10 @@ int extend_batch(st_problem *p, int64_t B, const st_samples &in, const st_extend
         if ((rc = edge_bufs_reserve(p->ebufs, B)) != ST_OK) return rc;
     }
     IterArgs a;
-    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools), 4096), nch_for(max_tiles(B, 2), 4096), 1024,
+    // node slices per scan tile: a budget of 4096 blocks for the nearest-node
+    // scan, 1024 for the bridge scan (its per-slice candidates are merged by
+    // the bridge check, which reads one per slice)
+    make_iter_args(p, B, in, out, nch_for(max_tiles(B, p->tree.n_pools), 4096), nch_for(max_tiles(B, 2), 1024), 1024,
                    B, a);
     const int blocks = (int)((B + 255) / 256);
     prof_mark(p, kStNearest, s);
