@@ -99,7 +99,9 @@ __device__ __forceinline__ int wave_bucket_add(int *bucket, int set) {
 
 // MULTI: many problems per launch; blockIdx.y picks the problem's record
 // (through the member list of its scene class) and blocks past the problem's
-// own grid leave at once.  The same convention holds for every kernel below.
+// own grid leave at once.  The kernels below follow this convention, except
+// the scans (member in blockIdx.z) and the bridge check (member in
+// blockIdx.x, so that members vary fastest).
 // Lanes per worker in the sampler: the arm's root check (q_g, T) shares the
 // spheres out among four lanes; every lane of a worker draws the same numbers.
 template <int KIND>
@@ -383,6 +385,7 @@ __global__ __launch_bounds__(TQ) void k_scan(ScanArgs a0, const ScanArgs *__rest
     const float U = a.use_snap ? pl->U_snap : pl->U;  // loaded ahead of the set-up barriers
     int4 tile;             // set, first query, queries, sigma
     int64_t qrow = -1;     // bucket row of the tile's queries (-1: identity order)
+    int64_t prow = -1;     // bridge buckets: the tile's first query in the two buckets' order
     if (a.bmode == 0) {
         if (t >= a.n_tiles[0]) return;
         tile = a.tiles[t];
@@ -417,6 +420,7 @@ __global__ __launch_bounds__(TQ) void k_scan(ScanArgs a0, const ScanArgs *__rest
         }
         tile = make_int4(set_id, kt * TQ, min(TQ, s_bc[sb] - kt * TQ), sg);
         qrow = (int64_t)sb * a.bstride;
+        if (a.bmode == 2) prow = (sb == 0 ? 0 : (int64_t)s_bc[0]) + (int64_t)kt * TQ;
     }
     const int set = tile.x, n = tile.z;
     const float sv = (float)tile.w * a.v;  // sigma * v
@@ -566,8 +570,11 @@ __global__ __launch_bounds__(TQ) void k_scan(ScanArgs a0, const ScanArgs *__rest
             }
         }
         if (!act || sub != 0) return;
-        a.pkey[(int64_t)q * a.pstride + blockIdx.y] = pk;
-        a.pidx[(int64_t)q * a.pstride + blockIdx.y] = (int32_t)pi;
+        // a bridge query's row: its place in the two buckets (the bridge
+        // check's wave index, known there before the worker is), else the query
+        const int64_t r = prow >= 0 ? prow + qs : q;
+        a.pkey[r * a.pstride + blockIdx.y] = pk;
+        a.pidx[r * a.pstride + blockIdx.y] = (int32_t)pi;
     } else {
         unsigned long long key = bi >= 0 ? pack_key(best, bi) : kNoKey;
         for (int o = 1; o < L; o <<= 1) {
@@ -950,9 +957,9 @@ __global__ __launch_bounds__(256) void k_bridge_check(BridgeArgs a0, EdgeArgs ea
     uint32_t bi = 0xffffffffu;
     if (in) {
         for (int y = lane; y < a.nch; y += 64) {
-            const int32_t ii = k.br_idx[(int64_t)w * a.nch + y];
+            const int32_t ii = k.br_idx[i * a.nch + y];
             if (ii < 0) continue;
-            const unsigned long long kk = k.br_key[(int64_t)w * a.nch + y];
+            const unsigned long long kk = k.br_key[i * a.nch + y];
             if (kk < bk || (kk == bk && (uint32_t)ii < bi)) {
                 bk = kk;
                 bi = (uint32_t)ii;
@@ -1666,7 +1673,7 @@ void make_iter_args(const st_problem *p, int64_t B, const st_samples &in, const 
     sb.keys = nullptr;
     sb.pkey = w.br_key;
     sb.pidx = w.br_idx;
-    sb.pstride = nch_br;  // query-major partials: [query][slice]
+    sb.pstride = nch_br;  // query-major partials: [bridge query in bucket order][slice]
     sb.nch = nch_br;
     BridgeArgs &ba = a.merge;
     ba.tree = p->tree;

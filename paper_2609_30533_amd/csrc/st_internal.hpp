@@ -149,8 +149,8 @@ struct Work {
     int32_t *parent, *new_idx;
     float *cost_new, *rootT_new;
     // bridges
-    unsigned long long *br_key;  // [NCH][B]
-    int32_t *br_idx;             // [NCH][B]
+    unsigned long long *br_key;  // [B][nch]: bridge query (in bucket order) x node slice
+    int32_t *br_idx;             // [B][nch]
     int32_t *bridge;
     float *xb;                   // [B][d+1]
     uint8_t *br_valid, *br_free;
