@@ -111,9 +111,9 @@ static int batch_build(st_batch *b) {
     int64_t tiles = 0;
     for (st_problem *p : b->mem) tiles += (p->prm.batch + 255) / 256 + 2;
     const int nch = (int)std::min<int64_t>(64, std::max<int64_t>(8, 8192 / std::max<int64_t>(tiles, 1)));
-    // item blocks per member: about 4096 over the batch, at least four each,
+    // item blocks per member: about 16384 over the batch, at least four each,
     // so that a member whose bridges are long spreads them over many waves
-    const int min_items = std::max(4, 4096 / P);
+    const int min_items = std::max(4, 16384 / P);
     int64_t all_edges = 0;
     for (st_problem *p : b->mem) all_edges += p->prm.batch;
     std::vector<SampleArgs> smp(P);
