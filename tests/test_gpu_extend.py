@@ -266,6 +266,9 @@ def test_plan_paths_validate(oracle_lib, name, make, iters, must):
         assert ok, msg
         assert res["U"] >= inf["L"] - 1e-5
         assert res["first_iter"] >= 0 and res["first_ms"] > 0
+        # device time of the iterations up to the first solution, inside the
+        # call's wall time (which adds the start check and the graph capture)
+        assert res["first_ms"] <= res["total_ms"]
 
 
 def test_roots_update_after_improvement(oracle_lib):
