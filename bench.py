@@ -758,8 +758,8 @@ def main():
     ap.add_argument("--static-ms", type=float, default=1000.0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (problems shard across GPUs "
-              "without exchange; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (independent problems would "
+              "shard across GPUs without exchange)", file=sys.stderr)
         sys.exit(2)
 
     import torch
