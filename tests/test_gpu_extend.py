@@ -90,6 +90,9 @@ PROBS = [
     # the root-recycling workload at its own shape: 7 DOF, 60 spheres, 32
     # obstacles on 16 waypoints, 64 slots, 8192 samples per iteration
     ("arm7-rr-full", lambda: scenes.arm7rr(2)),
+    # the 6-DOF arm workload at its own shape (4096 samples per iteration,
+    # the launch shapes the benchmark times)
+    ("arm6-ir-full", lambda: scenes.arm6(2)),
 ]
 # largest fraction of workers with an exempt decision that may end differently
 # (measured on MI355X: at most 0.83 %, disc2d-rr; 0 of 4452 exempt workers in
@@ -493,7 +496,8 @@ def test_capacity_exhausted_is_reported(oracle_lib):
     ("arm6-ir", lambda: _small(scenes.arm6(2), 1024, 1 << 15, 1 << 12, 8)),
     ("arm7-rr", lambda: _small(scenes.arm7rr(2, n_obs=16), 1024, 1 << 15, 1 << 12, 16)),
     ("disc2d-ir", lambda: _small(scenes.disc2d(3), 512)),
-], ids=["arm6-ir", "arm7-rr", "disc2d-ir"])
+    ("arm6-ir-full", lambda: scenes.arm6(2)),
+], ids=["arm6-ir", "arm7-rr", "disc2d-ir", "arm6-ir-full"])
 def test_iterate_equals_sample_and_extend(name, make):
     """The planner's own iterations (the sampler buckets its workers by node
     set, the extend step runs without the separate bucketing kernel, graph
