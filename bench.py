@@ -401,6 +401,43 @@ def ttfs_section(lib, args, validate):
             "queue_setup_ms_learned_batched": float(lq["setup_ms"]),
             "queue_wall_ms_learned_batched": float(lq["setup_ms"] + lq["total_ms"]),
         })
+
+    # final arrival at equal time for the workload: the first A evaluation
+    # problems, plain one after another with an equal share of the budget each
+    # (its start check and graph capture inside its share) against the learned
+    # batch with the whole budget (its set-up before it)
+    A = min(args.arrival_problems, n)
+    if A > 0:
+        share = args.arrival_ms / A
+        progress("arrival at equal time: %d problems, plain %.1f ms each, learned batch %.0f ms" % (
+            A, share, args.arrival_ms))
+        up = {}
+        for i in range(A):
+            p = _with(base[i][1], 4096, 1 << 18, 1 << 16, 1)
+            g = lib.Problem(p)
+            r = g.plan(max_ms=share, iters_per_sync=8)
+            if r["rc"] == 0 and r["first_iter"] >= 0:
+                up[i] = float(r["U"])
+                validate.append((p, r["states"], r["U"], r["C"]))
+            g.close()
+        bp = [_with(base[i][1], args.ttfs_batch_samples, 1 << 16, 1 << 13, 1) for i in range(A)]
+        lb = batched_run(lib, bp, args.arrival_ms, proposal=trained, keep_paths=True,
+                         lanes_bridge=args.ttfs_lanes_bridge)
+        ub = {}
+        for i, path in lb["paths"].items():
+            if path["rc"] == 0:
+                ub[i] = float(path["U"])
+                validate.append((bp[i], path["states"], path["U"], path["C"]))
+        ac = sorted(set(up) & set(ub))
+        out.update({
+            "arrival_workload": "the first %d evaluation problems, %.0f ms in all: plain one after another with "
+                                "%.1f ms each (set-up inside), learned+batched with the whole budget; mean final "
+                                "arrival over problems both solve" % (A, args.arrival_ms, share),
+            "arrival_solved_plain": len(up), "arrival_solved_learned_batched": len(ub), "arrival_common": len(ac),
+            "arrival_mean_plain": mean([up[i] for i in ac]),
+            "arrival_mean_learned_batched": mean([ub[i] for i in ac]),
+            "arrival_pairs_learned_batched_earlier": float(np.mean([ub[i] < up[i] for i in ac])) if ac else None,
+        })
     return out
 
 
@@ -732,6 +769,9 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the disc and recycling configuration rows")
     ap.add_argument("--queue-problems", type=int, default=128, help="problems of the workload comparison (0: skip)")
     ap.add_argument("--queue-ms", type=float, default=100.0)
+    ap.add_argument("--arrival-problems", type=int, default=128,
+                    help="problems of the equal-time arrival comparison (0: skip)")
+    ap.add_argument("--arrival-ms", type=float, default=2560.0, help="budget of the whole arrival workload")
     ap.add_argument("--batch-problems", type=int, default=512, help="heterogeneous batch size (0: skip)")
     ap.add_argument("--batch-ms", type=float, default=2000.0)
     ap.add_argument("--batch-obstacle-tile", type=int, default=16,
