@@ -474,7 +474,9 @@ int st_set_state_split(st_problem *p, int32_t split_extension, int32_t split_bri
  * consecutive edges (edges_per_block 1..8), lays their states end to end and
  * deals them to its waves in rounds of 64.
  * 0 selects the chunked path that bridges and st_check_edges use.  Results do
- * not depend on this.  Default 4.  Synchronous; drops captured graphs. */
+ * not depend on this.  Default 4.  In a batch (st_batch_create) a member on
+ * the flattened path takes 8 (fewer, fuller blocks for many members).
+ * Synchronous; drops captured graphs. */
 int st_set_flat_extension(st_problem *p, int32_t edges_per_block);
 
 /* ---- measurement ---------------------------------------------------------- */
